@@ -1,0 +1,156 @@
+/*
+ * vofl.h -- C ABI of libvofl: the matrix-free variable-order fractional
+ * Laplacian and the second-order time-splitting Fourier pseudospectral
+ * (TSFP2) wave solver of Zhang, Zhao and Zhou, "Fourier pseudospectral methods
+ * for the variable-order space fractional wave equations" (arXiv 2311.13049),
+ * on AMD Instinct MI355X (gfx950).
+ *
+ * Problem (Section 1, eq. (1.1); Section 2 for the grid):
+ *   (1/c^2) u_tt = eta (-Lap)^{1+gamma(x)} u + tau d/dt[(-Lap)^{1/2+gamma(x)} u]
+ * on a periodic box [lo, hi) with n[i] points per axis (n even), with
+ *   c = c0 cos(pi gamma/2), eta = -c0^{2 gamma} omega0^{-2 gamma} cos(pi gamma),
+ *   tau = -c0^{2 gamma - 1} omega0^{-2 gamma} sin(pi gamma), gamma = atan(1/Q)/pi.
+ * Written as u_t = v, v_t = -A(x) L1 u - B(x) L2 v with A = -c^2 eta,
+ * B = -c^2 tau, L1 = (-Lap)^{1+gamma(x)}, L2 = (-Lap)^{1/2+gamma(x)}.
+ *
+ * The generic model (1.5), u_tt = -kappa (-Lap)^{s(x)} u + lambda u^3, is
+ * selected with model = VOFL_MODEL_GENERIC (then s replaces gamma/Q and
+ * L1 = (-Lap)^{s(x)}).
+ *
+ * Discrete operator (eq. (2.13)): with s0 the grid mean of s,
+ * delta = s - s0, l_m(k) = (ln|mu_k|^2)^m / m!,
+ *   (L u)_j = sum_{m=0..M} delta_j^m  IDFT[ l_m |mu|^{2 s0} u_hat ]_j ,
+ * u_hat = DFT(u)/N, mu_k = 2 pi k / L per axis, the k = 0 term omitted.
+ *
+ * Arrays are real, C-ordered (last index fastest), in the plan's precision
+ * (double for VOFL_FP64, float for VOFL_FP32). Device pointers are HIP device
+ * memory owned by the caller (for example torch tensors); host pointers are
+ * read during vofl_plan only. Every call returns VOFL_OK (0) or a negative
+ * status; vofl_last_error() returns the message of the calling thread's last
+ * failure. No call allocates device memory after vofl_plan.
+ */
+#ifndef VOFL_H
+#define VOFL_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* status codes */
+#define VOFL_OK              0
+#define VOFL_ERR_INVALID    -1  /* argument outside the documented domain           */
+#define VOFL_ERR_NOMEM      -2  /* device allocation failed or hbm_budget exceeded   */
+#define VOFL_ERR_DEVICE     -3  /* HIP runtime error (no device, launch failure)     */
+#define VOFL_ERR_UNSTABLE   -4  /* a non-finite value appeared (time step too large,
+                                   see the stability condition (3.5))               */
+#define VOFL_ERR_UNSUPPORTED -5 /* grid size without a compiled FFT length           */
+
+/* precision of the transforms and pointwise work; the expansion coefficients,
+   the spectral multipliers, the propagator and the spectral state are FP64 in
+   both */
+#define VOFL_FP64 0
+#define VOFL_FP32 1
+
+/* models */
+#define VOFL_MODEL_SEISMIC 0   /* eq. (1.1), gamma(x) from Q(x) or given      */
+#define VOFL_MODEL_GENERIC 1   /* eq. (1.5), s(x) given, f(u) = lambda u^3      */
+
+/* operators for vofl_apply */
+#define VOFL_OP_S1 1   /* (-Lap)^{1+gamma(x)} (seismic) or (-Lap)^{s(x)} (generic) */
+#define VOFL_OP_S2 2   /* (-Lap)^{1/2+gamma(x)} (seismic model only)                */
+
+typedef struct vofl_desc {
+    int ndim;            /* 1, 2 or 3                                                  */
+    int n[3];            /* points per axis, even, first ndim entries used             */
+    double lo[3], hi[3]; /* periodic box [lo, hi) per axis, hi > lo                    */
+    int model;           /* VOFL_MODEL_SEISMIC or VOFL_MODEL_GENERIC                   */
+    double c0, omega0;   /* seismic: phase velocity and reference frequency, > 0       */
+    const double* Q;     /* seismic: host, N values, Q > 0 (+inf gives gamma = 0), or NULL */
+    const double* gamma; /* seismic: host, N values in [0, 1/2), or NULL; exactly one of Q, gamma */
+    const double* s;     /* generic: host, N values in (0, 2)                           */
+    double kappa;        /* generic: kappa > 0                                          */
+    double lambda;       /* generic: coefficient of the cubic term f(u) = lambda u^3    */
+    int M;               /* upper index of the expansion (M+1 terms), 0 <= M <= 64     */
+    double dt;           /* time step > 0                                              */
+    int precision;       /* VOFL_FP64 or VOFL_FP32                                     */
+    int max_batch;       /* largest nfields accepted by vofl_apply (>= 1; 0 means 1)   */
+    int batch;           /* independent solves advanced together by vofl_step (0 means 1);
+                            u and v then hold batch * N values, solve after solve      */
+    int coef_per_solve;  /* 0: one coefficient field (Q, gamma or s: N values) shared by
+                            all solves; 1: batch fields (batch * N values), one per solve */
+    size_t hbm_budget;   /* bytes of device memory the plan may take; 0 = no limit     */
+} vofl_desc;
+
+typedef struct vofl_plan_s* vofl_plan_t;
+
+/* Build a plan (Section 2.3 grid and symbol, eq. (2.13) expansion,
+ * eqs. (3.10)-(3.11) propagator): validates the descriptor on the host,
+ * computes gamma = atan(1/Q)/pi, the grid means, delta, A(x), B(x) in FP64,
+ * uploads the per-axis tables and allocates all device workspace.
+ * stream: HIP stream (hipStream_t) used for the uploads; may be NULL.
+ * On success *out owns all device memory of the plan. Errors:
+ * VOFL_ERR_INVALID (bad descriptor), VOFL_ERR_UNSUPPORTED (no FFT length),
+ * VOFL_ERR_NOMEM (allocation failed or footprint above hbm_budget),
+ * VOFL_ERR_DEVICE (no HIP device). The descriptor and host arrays are not
+ * retained. */
+int vofl_plan(const vofl_desc* desc, void* stream, vofl_plan_t* out);
+
+/* Device bytes a plan for desc would allocate (same validation as vofl_plan,
+ * no device access). Returns VOFL_OK and writes *bytes, or an error code. */
+int vofl_plan_footprint(const vofl_desc* desc, size_t* bytes);
+
+/* Apply the M-term operator (2.13) to nfields real fields:
+ * out_f = (L_op u_f) for f < nfields, with op VOFL_OP_S1 or VOFL_OP_S2.
+ * u, out: device, nfields * N values each, plan precision, out != u,
+ * no overlap. Asynchronous on stream. 1 <= nfields <= max_batch; with
+ * coef_per_solve = 1, field f uses solve f's coefficients (nfields <= batch). */
+int vofl_apply(vofl_plan_t plan, int op, const void* u, void* out, int nfields,
+               void* stream);
+
+/* Advance (u, v = u_t) by nsteps TSFP2 steps (eqs. (3.13)-(3.14); for (1.1)
+ * the exact part is the damped oscillator of the mean orders and the kick
+ * carries the variable-order remainder). u, v: device, N values each,
+ * overwritten in place. nsteps >= 0. Asynchronous on stream; a non-finite
+ * value sets the plan's device flag, reported as VOFL_ERR_UNSTABLE by the
+ * next vofl_sync_status (and by later vofl_step calls after a sync). */
+int vofl_step(vofl_plan_t plan, void* u, void* v, int nsteps, void* stream);
+
+/* u = u0, v = v0, then nsteps steps as vofl_step. u0/v0 may equal u/v. */
+int vofl_solve(vofl_plan_t plan, const void* u0, const void* v0, int nsteps,
+               void* u, void* v, void* stream);
+
+/* Advance several independent solves, one plan each, by nsteps[i] steps,
+ * issuing the launches of all solves interleaved on one stream so the
+ * device overlaps them. Plans may differ in grid, M and precision. Each
+ * solve's result equals what vofl_step gives for it alone. */
+int vofl_step_batch(vofl_plan_t* plans, void** u, void** v, const int* nsteps,
+                    int count, void* stream);
+
+/* Synchronize stream, then report VOFL_ERR_UNSTABLE if the plan's
+ * non-finite flag is set (the flag is cleared by the read). */
+int vofl_sync_status(vofl_plan_t plan, void* stream);
+
+/* Record per-kernel-class device time (HIP events) during later calls;
+ * enable = 0 stops recording. vofl_kernel_times writes up to cap entries of
+ * (name, total milliseconds, launch count) for the kernel classes seen since
+ * the last reset and returns their number. */
+int vofl_set_timing(vofl_plan_t plan, int enable);
+int vofl_kernel_times(vofl_plan_t plan, const char** names, double* ms,
+                      long long* launches, int cap);
+
+/* Plan scalars (FP64): out[0] = gbar (or s0), out[1] = kappa0, out[2] = beta0,
+ * out[3] = N, out[4] = device bytes held. Returns VOFL_OK. */
+int vofl_plan_info(vofl_plan_t plan, double* out, int cap);
+
+int vofl_destroy(vofl_plan_t plan);
+const char* vofl_last_error(void);
+/* Library version string. */
+const char* vofl_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* VOFL_H */

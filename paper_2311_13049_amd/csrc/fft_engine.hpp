@@ -1,0 +1,247 @@
+// Device-side FFT building blocks for gfx950 (64-wide wavefronts).
+//
+// A length-N transform ("pencil") is spread over TP = N/E threads; thread t
+// of a pencil holds the E elements t + TP*e (e = 0..E-1) in registers, both
+// before and after the transform, so global loads and stores of a pencil are
+// coalesced. The transform is a Stockham autosort FFT: each stage does E/R
+// radix-R butterflies per thread in registers, and stages exchange data
+// through LDS (one write + one read per element per exchange). Twiddles come
+// from a per-axis FP64-accurate table tw[j] = exp(-2 pi i j/N) rounded to the
+// working precision. DIR = -1 is the forward DFT sum_j x_j e^{-2 pi i jk/N},
+// DIR = +1 the unscaled inverse.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+namespace vofl {
+
+template <typename T>
+struct alignas(2 * sizeof(T)) cpx {
+    T x, y;
+};
+
+template <typename T>
+__device__ __forceinline__ cpx<T> cadd(cpx<T> a, cpx<T> b) { return {a.x + b.x, a.y + b.y}; }
+template <typename T>
+__device__ __forceinline__ cpx<T> csub(cpx<T> a, cpx<T> b) { return {a.x - b.x, a.y - b.y}; }
+template <typename T>
+__device__ __forceinline__ cpx<T> cmul(cpx<T> a, cpx<T> b) {
+    return {a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x};
+}
+template <typename T>
+__device__ __forceinline__ cpx<T> cscale(cpx<T> a, T s) { return {a.x * s, a.y * s}; }
+// multiply by -i (DIR = -1) or +i (DIR = +1)
+template <int DIR, typename T>
+__device__ __forceinline__ cpx<T> mul_i(cpx<T> a) {
+    if constexpr (DIR < 0) return {a.y, -a.x};
+    else return {-a.y, a.x};
+}
+// twiddle from the forward table: forward uses w, inverse uses conj(w)
+template <int DIR, typename T>
+__device__ __forceinline__ cpx<T> twmul(cpx<T> a, cpx<T> w) {
+    if constexpr (DIR > 0) w.y = -w.y;
+    return cmul(a, w);
+}
+
+// ---------------------------------------------------------------------------
+// small DFTs in registers
+// ---------------------------------------------------------------------------
+template <int DIR, typename T>
+__device__ __forceinline__ void dft2(cpx<T>* v) {
+    cpx<T> a = v[0];
+    v[0] = cadd(a, v[1]);
+    v[1] = csub(a, v[1]);
+}
+
+template <int DIR, typename T>
+__device__ __forceinline__ void dft3(cpx<T>* v) {
+    const T h = T(0.86602540378443864676);  // sqrt(3)/2
+    cpx<T> s = cadd(v[1], v[2]);
+    cpx<T> d = csub(v[1], v[2]);
+    cpx<T> m = {v[0].x - T(0.5) * s.x, v[0].y - T(0.5) * s.y};
+    cpx<T> r = mul_i<DIR>(cscale(d, h));  // DIR*i*(sqrt3/2)(v1 - v2)
+    v[0] = cadd(v[0], s);
+    v[1] = cadd(m, r);
+    v[2] = csub(m, r);
+}
+
+template <int DIR, typename T>
+__device__ __forceinline__ void dft4(cpx<T>* v) {
+    cpx<T> a0 = cadd(v[0], v[2]);
+    cpx<T> a1 = csub(v[0], v[2]);
+    cpx<T> a2 = cadd(v[1], v[3]);
+    cpx<T> a3 = mul_i<DIR>(csub(v[1], v[3]));
+    v[0] = cadd(a0, a2);
+    v[2] = csub(a0, a2);
+    v[1] = cadd(a1, a3);
+    v[3] = csub(a1, a3);
+}
+
+template <int DIR, typename T>
+__device__ __forceinline__ void dft8(cpx<T>* v) {
+    const T r2 = T(0.70710678118654752440);
+    cpx<T> e[4] = {v[0], v[2], v[4], v[6]};
+    cpx<T> o[4] = {v[1], v[3], v[5], v[7]};
+    dft4<DIR>(e);
+    dft4<DIR>(o);
+    // o[k] *= W8^k, W8 = exp(DIR * i pi/4)
+    cpx<T> o1 = o[1], o3 = o[3];
+    if constexpr (DIR < 0) {
+        o[1] = {r2 * (o1.x + o1.y), r2 * (o1.y - o1.x)};
+        o[3] = {r2 * (-o3.x + o3.y), r2 * (-o3.y - o3.x)};
+    } else {
+        o[1] = {r2 * (o1.x - o1.y), r2 * (o1.y + o1.x)};
+        o[3] = {r2 * (-o3.x - o3.y), r2 * (-o3.y + o3.x)};
+    }
+    o[2] = mul_i<DIR>(o[2]);
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        v[k] = cadd(e[k], o[k]);
+        v[k + 4] = csub(e[k], o[k]);
+    }
+}
+
+template <int DIR, typename T>
+__device__ __forceinline__ void dft16(cpx<T>* v) {
+    // n = 4*n1 + n2, k = k1 + 4*k2: DFT4 over n1, twiddle W16^{n2 k1}, DFT4 over n2
+    cpx<T> y[4][4];
+#pragma unroll
+    for (int n2 = 0; n2 < 4; ++n2) {
+        cpx<T> a[4] = {v[n2], v[4 + n2], v[8 + n2], v[12 + n2]};
+        dft4<DIR>(a);
+#pragma unroll
+        for (int k1 = 0; k1 < 4; ++k1) y[n2][k1] = a[k1];
+    }
+    const T c1 = T(0.92387953251128675613), s1 = T(0.38268343236508977173);
+    const T r2 = T(0.70710678118654752440);
+    // W16^j for j = n2*k1 in {1,2,3,4,6,9}; forward exp(-2 pi i j/16)
+    auto tw = [&](cpx<T> a, int j) -> cpx<T> {
+        T c, s;
+        switch (j) {
+            case 1: c = c1; s = s1; break;
+            case 2: c = r2; s = r2; break;
+            case 3: c = s1; s = c1; break;
+            case 4: c = T(0); s = T(1); break;
+            case 6: c = -r2; s = r2; break;
+            case 9: c = -c1; s = -s1; break;
+            default: c = T(1); s = T(0); break;
+        }
+        // forward: multiply by (c - i s); inverse: (c + i s)
+        if constexpr (DIR < 0) return {a.x * c + a.y * s, a.y * c - a.x * s};
+        else return {a.x * c - a.y * s, a.y * c + a.x * s};
+    };
+#pragma unroll
+    for (int n2 = 1; n2 < 4; ++n2)
+#pragma unroll
+        for (int k1 = 1; k1 < 4; ++k1) y[n2][k1] = tw(y[n2][k1], n2 * k1);
+#pragma unroll
+    for (int k1 = 0; k1 < 4; ++k1) {
+        cpx<T> b[4] = {y[0][k1], y[1][k1], y[2][k1], y[3][k1]};
+        dft4<DIR>(b);
+#pragma unroll
+        for (int k2 = 0; k2 < 4; ++k2) v[k1 + 4 * k2] = b[k2];
+    }
+}
+
+template <int R, int DIR, typename T>
+__device__ __forceinline__ void dft(cpx<T>* v) {
+    if constexpr (R == 2) dft2<DIR>(v);
+    else if constexpr (R == 3) dft3<DIR>(v);
+    else if constexpr (R == 4) dft4<DIR>(v);
+    else if constexpr (R == 8) dft8<DIR>(v);
+    else if constexpr (R == 16) dft16<DIR>(v);
+    else static_assert(R == 1, "unsupported radix");
+}
+
+// radix of the next stage: the largest of 16, 8, 4, 3, 2 dividing both the
+// remaining length and E
+constexpr int pick_radix(int rem, int E) {
+    return (rem % 16 == 0 && E % 16 == 0) ? 16
+         : (rem % 8 == 0 && E % 8 == 0)   ? 8
+         : (rem % 4 == 0 && E % 4 == 0)   ? 4
+         : (rem % 3 == 0 && E % 3 == 0)   ? 3
+         : (rem % 2 == 0 && E % 2 == 0)   ? 2
+                                          : 1;
+}
+constexpr int num_stages(int N, int E) {
+    int s = 0, rem = N;
+    while (rem > 1) {
+        int r = pick_radix(rem, E);
+        if (r == 1) return -1;
+        rem /= r;
+        ++s;
+    }
+    return s;
+}
+
+// LDS views. Pencil-major: element i of a pencil at base[i + i/16]
+// (one pad slot per 16 elements). Column-interleaved: element i of column c
+// at base[i*W + c] (columns of a tile side by side).
+template <typename T>
+struct LdsPencil {
+    cpx<T>* base;
+    __device__ __forceinline__ cpx<T>& operator[](int i) const { return base[i + (i >> 4)]; }
+    static constexpr int footprint(int N) { return N + N / 16; }
+};
+template <typename T, int W>
+struct LdsColumn {
+    cpx<T>* base;  // already offset by the column index
+    __device__ __forceinline__ cpx<T>& operator[](int i) const { return base[i * W]; }
+    static constexpr int footprint(int N) { return N * W; }
+};
+
+// One Stockham stage with stride NS (product of the radices done before).
+template <typename T, int N, int E, int DIR, int NS, class Lds>
+__device__ __forceinline__ void fft_stages(cpx<T> (&v)[E], const int t, const Lds& lds,
+                                           const cpx<T>* __restrict__ tw) {
+    constexpr int R = pick_radix(N / NS, E);
+    static_assert(R > 1, "length not supported by the radix set");
+    constexpr int TP = N / E;
+    constexpr int Q = E / R;  // butterflies per thread in this stage
+    constexpr bool LAST = (NS * R == N);
+    cpx<T> out[E];
+#pragma unroll
+    for (int q = 0; q < Q; ++q) {
+        const int b = t + q * TP;  // butterfly index in [0, N/R)
+        cpx<T> w[R];
+#pragma unroll
+        for (int r = 0; r < R; ++r) w[r] = v[q + r * Q];
+        if constexpr (NS > 1) {
+            const int k = b % NS;
+#pragma unroll
+            for (int r = 1; r < R; ++r) w[r] = twmul<DIR>(w[r], tw[k * r * (N / (NS * R))]);
+        }
+        dft<R, DIR>(w);
+        if constexpr (LAST) {
+#pragma unroll
+            for (int r = 0; r < R; ++r) out[q + r * Q] = w[r];
+        } else {
+            const int k = b % NS;
+            const int base = (b / NS) * NS * R + k;
+#pragma unroll
+            for (int r = 0; r < R; ++r) lds[base + r * NS] = w[r];
+        }
+    }
+    if constexpr (LAST) {
+#pragma unroll
+        for (int e = 0; e < E; ++e) v[e] = out[e];
+    } else {
+        __syncthreads();
+#pragma unroll
+        for (int e = 0; e < E; ++e) v[e] = lds[t + e * TP];
+        __syncthreads();
+        fft_stages<T, N, E, DIR, NS * R>(v, t, lds, tw);
+    }
+}
+
+// Full length-N transform of the pencil held as v[e] = x[t + TP*e].
+// Every thread of the workgroup must call this (it contains barriers).
+template <typename T, int N, int E, int DIR, class Lds>
+__device__ __forceinline__ void fft_pencil(cpx<T> (&v)[E], const int t, const Lds& lds,
+                                           const cpx<T>* __restrict__ tw) {
+    static_assert(N % E == 0, "E must divide N");
+    static_assert(num_stages(N, E) > 0, "length not supported");
+    fft_stages<T, N, E, DIR, 1>(v, t, lds, tw);
+}
+
+}  // namespace vofl

@@ -1,0 +1,890 @@
+// HIP kernels of the variable-order operator (2.13) and the TSFP2 step
+// (3.13) on gfx950.
+//
+// Spectral layout: a real field of shape (n0[, n1][, n2]) has its spectrum
+// stored for k0 = 0..n0/2 only ("half" along the OUTERMOST axis, Hermitian
+// symmetry gives the rest), as complex [n0/2+1][n1][n2] (3D) or
+// [n0/2+1][n1] (2D), last index fastest. Transforms along the last
+// (contiguous) axis run on pencils; the other axes run on tiles of W
+// consecutive columns, so every global access is coalesced along the last
+// axis. The real<->half step happens along axis 0, inside the kernels that
+// read/write physical data, where a column of a tile is a whole line.
+//
+// Kernel classes:
+//   k_contig   last-axis transforms fused with the spectral pointwise work:
+//              the 1/N scale, the kick update v_hat += dt*dv_hat, the exact
+//              damped-oscillator sub-step (3.10)-(3.11), and the M+1 (or
+//              2(M+1)) multiplied term spectra l_m |mu|^{2 sigma} u_hat of
+//              (2.13), each inverse-transformed along the last axis.
+//   k_mid      3D middle-axis C2C transforms of a range of fields (tiles).
+//   k_r2c0     axis-0 forward transform of real fields (tiles), half output.
+//   k_c2r0     axis-0 inverse transform of pairs of half spectra (two real
+//              results from one complex transform) fused with the
+//              delta-power sum of (2.13) and either the operator output, the
+//              kick right-hand side plus its forward axis-0 transform, or the
+//              export of (u, v).
+//   k_1d_*     whole 1D apply / step loop of one field per workgroup in LDS.
+#pragma once
+
+#include "fft_engine.hpp"
+
+namespace vofl {
+
+enum InKind : int { IN_APPLY = 0, IN_INIT = 1, IN_KICK = 2 };
+enum EmitKind : int { EMIT_NONE = 0, EMIT_APPLY = 1, EMIT_STEP = 2, EMIT_EXPORT = 3, EMIT_GENERIC = 4 };
+enum C2RMode : int { C2R_APPLY = 0, C2R_KICK = 1, C2R_EXPORT = 2, C2R_KICK_GENERIC = 3 };
+enum ModelKind : int { MODEL_SEISMIC = 0, MODEL_GENERIC = 1 };
+
+// Per-solve scalars: mean orders sig1 (1+gbar or s0) and sig2 (1/2+gbar),
+// exact-part coefficients kappa0 = A(gbar), beta0 = B(gbar), and the
+// coefficient of the cubic term (generic model).
+struct SolveScalars {
+    double sig1, sig2, kappa0, beta0, lambda, pad0, pad1, pad2;
+};
+
+// ---------------------------------------------------------------------------
+// pointwise helpers (FP64)
+// ---------------------------------------------------------------------------
+
+// Exact flow over time t of u' = v, v' = -kappa0 P1 u - beta0 P2 v (one mode).
+// b = beta0 P2/2, q = kappa0 P1, w^2 = q - b^2; the k = 0 mode (P1 = P2 = 0)
+// gives u += t v (eq. (3.11)); beta0 = 0 gives the rotation (3.10).
+__device__ __noinline__ void overdamped_cs(double w2m, double t, double& C, double& S) {
+    const double w = sqrt(w2m);
+    C = cosh(w * t);
+    S = sinh(w * t) / w;
+}
+
+__device__ __forceinline__ void damped_flow(double P1, double P2, double kappa0, double beta0,
+                                            double t, double& g11, double& g12, double& g21,
+                                            double& g22) {
+    const double b = 0.5 * beta0 * P2;
+    const double q = kappa0 * P1;
+    const double w2 = q - b * b;
+    double C, S;
+    if (w2 > 0.0) {
+        const double w = sqrt(w2);
+        double sn, cs;
+        sincos(w * t, &sn, &cs);
+        C = cs;
+        S = sn / w;
+    } else if (w2 < 0.0) {
+        overdamped_cs(-w2, t, C, S);
+    } else {
+        C = 1.0;
+        S = t;
+    }
+    const double e = (b != 0.0) ? exp(-b * t) : 1.0;
+    g11 = e * (C + b * S);
+    g12 = e * S;
+    g21 = -e * q * S;
+    g22 = e * (C - b * S);
+}
+
+template <typename T>
+__device__ __forceinline__ cpx<double> to_d(cpx<T> a) {
+    return {double(a.x), double(a.y)};
+}
+template <typename T>
+__device__ __forceinline__ cpx<T> from_d(cpx<double> a) {
+    return {T(a.x), T(a.y)};
+}
+
+// Tile width (columns per workgroup) of the strided kernels: the widest of
+// 16/8/4 whose staged half columns fit in about 66 KB of LDS.
+template <typename T, int N>
+constexpr int tile_width() {
+    constexpr int col = (N + 2) * int(sizeof(cpx<T>));
+    return (16 * col <= 67584) ? 16 : (8 * col <= 67584) ? 8 : 4;
+}
+// Tile width of k_c2r0, which also keeps 8 elements per thread within 512
+// threads per workgroup (register budget of the fused kick).
+template <typename T, int N>
+constexpr int c2r_width() {
+    constexpr int w = tile_width<T, N>();
+    constexpr int lim = (4096 / N) < 4 ? 4 : (4096 / N);
+    return w < lim ? w : lim;
+}
+
+// ---------------------------------------------------------------------------
+// k_contig: last-axis pencils
+// ---------------------------------------------------------------------------
+template <typename T>
+struct ContigArgs {
+    const cpx<T>* in;        // input half fields: item b, field f at in + (b*in_slots + in_slot0 + f)*H
+    int in_slots, in_slot0, nin;
+    cpx<double>* U;          // spectral state u_hat, item b at U + b*H
+    cpx<double>* V;          // spectral state v_hat
+    cpx<T>* out;             // output slots: item b, slot s at out + (b*out_slots + out_slot0 + s)*H
+    int out_slots, out_slot0;
+    long long H;             // complex elements of one half field
+    int npencils;            // pencils of one field
+    int n1;                  // pencils per k0 plane (3D: n1, 2D: 1)
+    const double* mu2_0;     // mu^2 of axis 0 by bin
+    const double* mu2_1;     // axis 1 (3D) or null
+    const double* mu2_l;     // last axis
+    const cpx<T>* tw;        // last-axis twiddle table
+    const SolveScalars* sc;  // per item (sc_stride 1) or shared (0)
+    int sc_stride;
+    int in_kind, emit_kind, do_prop, M, op;
+    double tprop, dt, invN;
+};
+
+template <typename T, int N, int E, int P>
+__global__ __launch_bounds__(P*(N / E)) void k_contig(ContigArgs<T> a) {
+    constexpr int TP = N / E;
+    constexpr int FP = LdsPencil<T>::footprint(N);
+    __shared__ cpx<T> lds_raw[P * FP];
+    const int lp = threadIdx.x / TP;
+    const int t = threadIdx.x % TP;
+    const int p = blockIdx.x * P + lp;
+    const int bi = blockIdx.y;
+    const bool active = p < a.npencils;
+    const int pc = active ? p : 0;
+    const LdsPencil<T> lds{lds_raw + lp * FP};
+    const int k0 = pc / a.n1;
+    const int k1 = pc % a.n1;
+    const double m2base = a.mu2_0[k0] + (a.mu2_1 ? a.mu2_1[k1] : 0.0);
+    const long long pen = (long long)pc * N;
+    const SolveScalars sc = a.sc[bi * a.sc_stride];
+
+    cpx<double> uh[E], vh[E];
+    if (a.in_kind == IN_KICK) {
+        cpx<T> d[E];
+        const cpx<T>* src = a.in + ((long long)bi * a.in_slots + a.in_slot0) * a.H + pen;
+#pragma unroll
+        for (int e = 0; e < E; ++e) d[e] = src[t + TP * e];
+        fft_pencil<T, N, E, -1>(d, t, lds, a.tw);
+        const cpx<double>* Us = a.U + (long long)bi * a.H + pen;
+        const cpx<double>* Vs = a.V + (long long)bi * a.H + pen;
+        const double s = a.dt * a.invN;
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+            uh[e] = Us[t + TP * e];
+            const cpx<double> vv = Vs[t + TP * e];
+            vh[e] = {vv.x + s * double(d[e].x), vv.y + s * double(d[e].y)};
+        }
+    } else {
+        for (int f = 0; f < a.nin; ++f) {
+            cpx<T> d[E];
+            const cpx<T>* src = a.in + ((long long)bi * a.in_slots + a.in_slot0 + f) * a.H + pen;
+#pragma unroll
+            for (int e = 0; e < E; ++e) d[e] = src[t + TP * e];
+            fft_pencil<T, N, E, -1>(d, t, lds, a.tw);
+#pragma unroll
+            for (int e = 0; e < E; ++e) {
+                const cpx<double> z = {double(d[e].x) * a.invN, double(d[e].y) * a.invN};
+                if (f == 0) uh[e] = z;
+                else vh[e] = z;
+            }
+        }
+        if (a.nin < 2) {
+#pragma unroll
+            for (int e = 0; e < E; ++e) vh[e] = {0.0, 0.0};
+        }
+    }
+
+    // per element: ln|mu|^2, the symbols |mu|^{2 sig} (zero at k = 0), the
+    // exact sub-step, the state store, and the first multiplier of the terms
+    double L[E];
+    cpx<double>* Ud = a.U + (long long)bi * a.H + pen;
+    cpx<double>* Vd = a.V + (long long)bi * a.H + pen;
+    const bool store_state = (a.in_kind != IN_APPLY) && active;
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+        const double m2 = m2base + a.mu2_l[t + TP * e];
+        double P1 = 0.0, P2 = 0.0;
+        L[e] = 0.0;
+        if (m2 > 0.0) {
+            L[e] = log(m2);
+            P1 = exp(sc.sig1 * L[e]);
+            P2 = exp(sc.sig2 * L[e]);
+        }
+        if (a.do_prop) {
+            double g11, g12, g21, g22;
+            damped_flow(P1, P2, sc.kappa0, sc.beta0, a.tprop, g11, g12, g21, g22);
+            const cpx<double> u0 = uh[e], v0 = vh[e];
+            uh[e] = {g11 * u0.x + g12 * v0.x, g11 * u0.y + g12 * v0.y};
+            vh[e] = {g21 * u0.x + g22 * v0.x, g21 * u0.y + g22 * v0.y};
+        }
+        if (store_state) {
+            Ud[t + TP * e] = uh[e];
+            Vd[t + TP * e] = vh[e];
+        }
+        if (a.emit_kind == EMIT_STEP) {
+            uh[e] = {P1 * uh[e].x, P1 * uh[e].y};
+            vh[e] = {P2 * vh[e].x, P2 * vh[e].y};
+        } else if (a.emit_kind == EMIT_GENERIC) {
+            vh[e] = uh[e];  // u_hat itself, for the nonlinear term
+            uh[e] = {P1 * uh[e].x, P1 * uh[e].y};
+        } else if (a.emit_kind == EMIT_APPLY) {
+            const double c = (a.op == 2) ? P2 : P1;
+            uh[e] = {c * uh[e].x, c * uh[e].y};
+        }
+    }
+
+    cpx<T>* dst0 = a.out + ((long long)bi * a.out_slots + a.out_slot0) * a.H + pen;
+    if (a.emit_kind == EMIT_GENERIC) {
+        // slot M+1: u_hat itself (inverse along the last axis)
+        {
+            cpx<T> x[E];
+#pragma unroll
+            for (int e = 0; e < E; ++e) x[e] = from_d<T>(vh[e]);
+            fft_pencil<T, N, E, +1>(x, t, lds, a.tw);
+            if (active) {
+                cpx<T>* d = dst0 + (long long)(a.M + 1) * a.H;
+#pragma unroll
+                for (int e = 0; e < E; ++e) d[t + TP * e] = x[e];
+            }
+        }
+    }
+    if (a.emit_kind == EMIT_APPLY || a.emit_kind == EMIT_GENERIC) {
+        // x_m = l_m |mu|^{2 sig} u_hat, l_{m+1} = l_m L/(m+1)
+        for (int m = 0; m <= a.M; ++m) {
+            cpx<T> x[E];
+#pragma unroll
+            for (int e = 0; e < E; ++e) x[e] = from_d<T>(uh[e]);
+            fft_pencil<T, N, E, +1>(x, t, lds, a.tw);
+            if (active) {
+                cpx<T>* d = dst0 + (long long)m * a.H;
+#pragma unroll
+                for (int e = 0; e < E; ++e) d[t + TP * e] = x[e];
+            }
+            const double inv = 1.0 / double(m + 1);
+#pragma unroll
+            for (int e = 0; e < E; ++e) {
+                const double f = L[e] * inv;
+                uh[e] = {uh[e].x * f, uh[e].y * f};
+            }
+        }
+    } else if (a.emit_kind == EMIT_STEP) {
+        for (int m = 0; m <= a.M; ++m) {
+            cpx<T> x[E];
+#pragma unroll
+            for (int e = 0; e < E; ++e) x[e] = from_d<T>(uh[e]);
+            fft_pencil<T, N, E, +1>(x, t, lds, a.tw);
+            if (active) {
+                cpx<T>* d = dst0 + (long long)(2 * m) * a.H;
+#pragma unroll
+                for (int e = 0; e < E; ++e) d[t + TP * e] = x[e];
+            }
+#pragma unroll
+            for (int e = 0; e < E; ++e) x[e] = from_d<T>(vh[e]);
+            fft_pencil<T, N, E, +1>(x, t, lds, a.tw);
+            if (active) {
+                cpx<T>* d = dst0 + (long long)(2 * m + 1) * a.H;
+#pragma unroll
+                for (int e = 0; e < E; ++e) d[t + TP * e] = x[e];
+            }
+            const double inv = 1.0 / double(m + 1);
+#pragma unroll
+            for (int e = 0; e < E; ++e) {
+                const double f = L[e] * inv;
+                uh[e] = {uh[e].x * f, uh[e].y * f};
+                vh[e] = {vh[e].x * f, vh[e].y * f};
+            }
+        }
+    } else if (a.emit_kind == EMIT_EXPORT) {
+        for (int f = 0; f < 2; ++f) {
+            cpx<T> x[E];
+#pragma unroll
+            for (int e = 0; e < E; ++e) x[e] = from_d<T>(f == 0 ? uh[e] : vh[e]);
+            fft_pencil<T, N, E, +1>(x, t, lds, a.tw);
+            if (active) {
+                cpx<T>* d = dst0 + (long long)f * a.H;
+#pragma unroll
+                for (int e = 0; e < E; ++e) d[t + TP * e] = x[e];
+            }
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// k_mid: 3D axis-1 C2C on a range of fields, in place
+// ---------------------------------------------------------------------------
+template <typename T>
+struct MidArgs {
+    cpx<T>* buf;            // item b, slot s at buf + (b*slots + s)*H
+    int slots, slot0, nf;   // fields [slot0, slot0 + nf) of each item
+    long long H;
+    int n2;                 // columns of a k0 plane (last axis length)
+    int tiles_per_plane;    // ceil(n2 / W)
+    const cpx<T>* tw;       // axis-1 twiddles
+};
+
+template <typename T, int N, int E, int W, int DIR>
+__global__ __launch_bounds__(W*(N / E)) void k_mid(MidArgs<T> a) {
+    constexpr int TP = N / E;
+    __shared__ cpx<T> lds_raw[N * W];
+    const int c = threadIdx.x % W;
+    const int t = threadIdx.x / W;
+    const int plane = blockIdx.x / a.tiles_per_plane;
+    const int col = (blockIdx.x % a.tiles_per_plane) * W + c;
+    const bool active = col < a.n2;
+    const int colc = active ? col : 0;
+    const int item = blockIdx.y / a.nf;
+    const int f = blockIdx.y % a.nf;
+    cpx<T>* base = a.buf + ((long long)item * a.slots + a.slot0 + f) * a.H +
+                   (long long)plane * N * a.n2 + colc;
+    const LdsColumn<T, W> lds{lds_raw + c};
+    cpx<T> v[E];
+#pragma unroll
+    for (int e = 0; e < E; ++e) v[e] = base[(long long)(t + TP * e) * a.n2];
+    fft_pencil<T, N, E, DIR>(v, t, lds, a.tw);
+    if (active) {
+#pragma unroll
+        for (int e = 0; e < E; ++e) base[(long long)(t + TP * e) * a.n2] = v[e];
+    }
+}
+
+// ---------------------------------------------------------------------------
+// k_r2c0: axis-0 forward transform of real fields -> half spectra
+// ---------------------------------------------------------------------------
+template <typename T>
+struct R2CArgs {
+    const T* in;            // real fields: item b, field f at in + (b*nf + f)*Nreal
+    int nf;
+    long long Nreal;
+    cpx<T>* out;            // half fields: item b, field f at out + (b*slots + slot0 + f)*H
+    int slots, slot0;
+    long long H;
+    int inner;              // columns (product of the other axes)
+    const cpx<T>* tw;       // axis-0 twiddles
+};
+
+template <typename T, int N, int E, int W>
+__global__ __launch_bounds__(W*(N / E)) void k_r2c0(R2CArgs<T> a) {
+    constexpr int TP = N / E;
+    __shared__ cpx<T> lds_raw[N * W];
+    const int c = threadIdx.x % W;
+    const int t = threadIdx.x / W;
+    const int col = blockIdx.x * W + c;
+    const bool active = col < a.inner;
+    const int colc = active ? col : 0;
+    const int item = blockIdx.y / a.nf;
+    const int f = blockIdx.y % a.nf;
+    const T* src = a.in + ((long long)item * a.nf + f) * a.Nreal + colc;
+    const LdsColumn<T, W> lds{lds_raw + c};
+    cpx<T> v[E];
+#pragma unroll
+    for (int e = 0; e < E; ++e) v[e] = {src[(long long)(t + TP * e) * a.inner], T(0)};
+    fft_pencil<T, N, E, -1>(v, t, lds, a.tw);
+    if (active) {
+        cpx<T>* dst = a.out + ((long long)item * a.slots + a.slot0 + f) * a.H + colc;
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+            const int k = t + TP * e;
+            if (k <= N / 2) {
+                cpx<T> z = v[e];
+                if (k == 0 || k == N / 2) z.y = T(0);
+                dst[(long long)k * a.inner] = z;
+            }
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// k_c2r0: axis-0 inverse of pairs of half spectra + (2.13) sum + epilogue
+// ---------------------------------------------------------------------------
+template <typename T>
+struct C2RArgs {
+    const cpx<T>* in;       // half slots: item b, slot s at in + (b*slots + s)*H
+    int slots;
+    long long H;
+    int inner;
+    const cpx<T>* tw;       // axis-0 twiddles
+    int mode, M, model;
+    // per-point coefficients (physical layout); stride 0 if shared by items
+    const double* delta;
+    const T* A;
+    const T* B;
+    long long coef_stride;
+    const SolveScalars* sc;
+    int sc_stride;
+    // outputs
+    cpx<T>* dv_out;         // kick: half field at dv_out + (b*slots + dv_slot)*H
+    int dv_slot;
+    T* r0;                  // apply: out; export: u (item b at r0 + b*Nreal)
+    T* r1;                  // export: v
+    long long Nreal;
+    int* flag;              // set to 1 on a non-finite kick value
+};
+
+// Y = a + i b, with a, b the Hermitian extensions of two half columns.
+template <typename T, int N, int W>
+__device__ __forceinline__ cpx<T> hermitian_pair(const cpx<T>* h1, const cpx<T>* h2, int c, int k) {
+    if (k <= N / 2) {
+        cpx<T> p = h1[k * W + c];
+        cpx<T> q = h2 ? h2[k * W + c] : cpx<T>{T(0), T(0)};
+        if (k == 0 || k == N / 2) {
+            p.y = T(0);
+            q.y = T(0);
+        }
+        return {p.x - q.y, p.y + q.x};
+    }
+    const int kk = N - k;
+    const cpx<T> p = h1[kk * W + c];
+    const cpx<T> q = h2 ? h2[kk * W + c] : cpx<T>{T(0), T(0)};
+    return {p.x + q.y, q.x - p.y};
+}
+
+template <typename T, int N, int E, int W>
+__global__ __launch_bounds__(W*(N / E)) void k_c2r0(C2RArgs<T> a) {
+    constexpr int TP = N / E;
+    constexpr int NT = W * TP;
+    constexpr int HR = N / 2 + 1;  // stored rows
+    // staging (two half columns) and the FFT exchange share one buffer:
+    // a barrier separates the reads of the staged rows from the transform
+    __shared__ cpx<T> lds_fft[2 * HR * W];
+    cpx<T>* h1 = lds_fft;
+    cpx<T>* h2 = lds_fft + HR * W;
+    const int c = threadIdx.x % W;
+    const int t = threadIdx.x / W;
+    const int col0 = blockIdx.x * W;
+    const int col = col0 + c;
+    const bool active = col < a.inner;
+    const int colc = active ? col : 0;
+    const int item = blockIdx.y;
+    const LdsColumn<T, W> lds{lds_fft + c};
+    const cpx<T>* ibase = a.in + (long long)item * a.slots * a.H;
+
+    // stage rows 0..N/2 of one or two half slots into LDS (coalesced)
+    auto stage = [&](int s1, int s2) {
+        for (int i = threadIdx.x; i < HR * W; i += NT) {
+            const int row = i / W, cc = i % W;
+            const int cg = col0 + cc;
+            const bool ok = cg < a.inner;
+            const long long off = (long long)row * a.inner + (ok ? cg : 0);
+            h1[i] = ibase[(long long)s1 * a.H + off];
+            if (s2 >= 0) h2[i] = ibase[(long long)s2 * a.H + off];
+        }
+        __syncthreads();
+    };
+
+    // delta at this thread's points (re-read from cache where needed)
+    const double* dptr = a.delta + (long long)item * a.coef_stride + colc;
+
+    if (a.mode == C2R_EXPORT) {
+        stage(0, 1);
+        cpx<T> y[E];
+#pragma unroll
+        for (int e = 0; e < E; ++e) y[e] = hermitian_pair<T, N, W>(h1, h2, c, t + TP * e);
+        __syncthreads();
+        fft_pencil<T, N, E, +1>(y, t, lds, a.tw);
+        if (active) {
+            T* u = a.r0 + (long long)item * a.Nreal + colc;
+            T* v = a.r1 + (long long)item * a.Nreal + colc;
+#pragma unroll
+            for (int e = 0; e < E; ++e) {
+                u[(long long)(t + TP * e) * a.inner] = y[e].x;
+                v[(long long)(t + TP * e) * a.inner] = y[e].y;
+            }
+        }
+        return;
+    }
+
+    if (a.mode == C2R_APPLY) {
+        // slots m (real part) and m+1 (imaginary part) in one transform
+        double acc[E], dp[E];
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+            acc[e] = 0.0;
+            dp[e] = 1.0;
+        }
+        for (int m = 0; m <= a.M; m += 2) {
+            const bool pair = (m + 1 <= a.M);
+            stage(m, pair ? m + 1 : -1);
+            cpx<T> y[E];
+#pragma unroll
+            for (int e = 0; e < E; ++e)
+                y[e] = hermitian_pair<T, N, W>(h1, pair ? h2 : nullptr, c, t + TP * e);
+            __syncthreads();
+            fft_pencil<T, N, E, +1>(y, t, lds, a.tw);
+            if (num_stages(N, E) < 2) __syncthreads();
+#pragma unroll
+            for (int e = 0; e < E; ++e) {
+                const double d = dptr[(long long)(t + TP * e) * a.inner];
+                acc[e] += dp[e] * (double(y[e].x) + d * double(y[e].y));
+                dp[e] *= d * d;
+            }
+        }
+        if (active) {
+            T* o = a.r0 + (long long)item * a.Nreal + colc;
+#pragma unroll
+            for (int e = 0; e < E; ++e) o[(long long)(t + TP * e) * a.inner] = T(acc[e]);
+        }
+        return;
+    }
+
+    if (a.mode == C2R_KICK_GENERIC) {
+        // slots s = 0..M: l_s |mu|^{2 s0} u_hat, slot M+1: u_hat; pairs (s, s+1) share
+        // one transform. dv = -kappa sum_{s=1..M} delta^s t_s + lambda u^3.
+        const SolveScalars sc = a.sc[item * a.sc_stride];
+        double acc[E], dp[E], uu[E];
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+            acc[e] = 0.0;
+            dp[e] = 1.0;
+            uu[e] = 0.0;
+        }
+        const int ns = a.M + 2;
+        for (int s0 = 0; s0 < ns; s0 += 2) {
+            const bool pair = (s0 + 1 < ns);
+            stage(s0, pair ? s0 + 1 : -1);
+            cpx<T> y[E];
+#pragma unroll
+            for (int e = 0; e < E; ++e)
+                y[e] = hermitian_pair<T, N, W>(h1, pair ? h2 : nullptr, c, t + TP * e);
+            __syncthreads();
+            fft_pencil<T, N, E, +1>(y, t, lds, a.tw);
+            if (num_stages(N, E) < 2) __syncthreads();
+#pragma unroll
+            for (int e = 0; e < E; ++e) {
+                const double d = dptr[(long long)(t + TP * e) * a.inner];
+                for (int h = 0; h < 2; ++h) {
+                    const int sidx = s0 + h;
+                    if (sidx >= ns) break;
+                    const double val = h == 0 ? double(y[e].x) : double(y[e].y);
+                    if (sidx == a.M + 1) {
+                        uu[e] = val;
+                    } else {
+                        if (sidx > 0) acc[e] -= sc.kappa0 * dp[e] * val;
+                        dp[e] *= d;
+                    }
+                }
+            }
+        }
+        cpx<T> z[E];
+        bool bad = false;
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+            const double dv = acc[e] + sc.lambda * uu[e] * uu[e] * uu[e];
+            bad |= !isfinite(dv);
+            z[e] = {T(dv), T(0)};
+        }
+        if (bad && active) a.flag[0] = 1;
+        fft_pencil<T, N, E, -1>(z, t, lds, a.tw);
+        if (active) {
+            cpx<T>* dst = a.dv_out + ((long long)item * a.slots + a.dv_slot) * a.H + colc;
+#pragma unroll
+            for (int e = 0; e < E; ++e) {
+                const int k = t + TP * e;
+                if (k <= N / 2) {
+                    cpx<T> w = z[e];
+                    if (k == 0 || k == N / 2) w.y = T(0);
+                    dst[(long long)k * a.inner] = w;
+                }
+            }
+        }
+        return;
+    }
+
+    // C2R_KICK: slots 2m (|mu|^{2 sig1} u_hat terms) and 2m+1 (|mu|^{2 sig2} v_hat terms).
+    // dv = (kappa0 - A) t1_0 + (beta0 - B) t2_0 + sum_{m>=1} delta^m (-A t1_m - B t2_m),
+    // with running coefficients a1 = -A delta^m, b1 = -B delta^m (FP64).
+    const SolveScalars sc = a.sc[item * a.sc_stride];
+    double acc[E], a1[E], b1[E];
+    {
+        const T* Ap = a.A + (long long)item * a.coef_stride + colc;
+        const T* Bp = a.B + (long long)item * a.coef_stride + colc;
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+            const long long off = (long long)(t + TP * e) * a.inner;
+            a1[e] = -double(Ap[off]);
+            b1[e] = -double(Bp[off]);
+            acc[e] = 0.0;
+        }
+    }
+    for (int m = 0; m <= a.M; ++m) {
+        stage(2 * m, 2 * m + 1);
+        cpx<T> y[E];
+#pragma unroll
+        for (int e = 0; e < E; ++e) y[e] = hermitian_pair<T, N, W>(h1, h2, c, t + TP * e);
+        __syncthreads();
+        fft_pencil<T, N, E, +1>(y, t, lds, a.tw);
+        if (num_stages(N, E) < 2) __syncthreads();
+        const double k0c = (m == 0) ? sc.kappa0 : 0.0;
+        const double b0c = (m == 0) ? sc.beta0 : 0.0;
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+            const double d = dptr[(long long)(t + TP * e) * a.inner];
+            acc[e] += (k0c + a1[e]) * double(y[e].x) + (b0c + b1[e]) * double(y[e].y);
+            a1[e] *= d;
+            b1[e] *= d;
+        }
+    }
+    cpx<T> z[E];
+    {
+        bool bad = false;
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+            bad |= !isfinite(acc[e]);
+            z[e] = {T(acc[e]), T(0)};
+        }
+        if (bad && active) a.flag[0] = 1;
+    }
+    fft_pencil<T, N, E, -1>(z, t, lds, a.tw);
+    if (active) {
+        cpx<T>* dst = a.dv_out + ((long long)item * a.slots + a.dv_slot) * a.H + colc;
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+            const int k = t + TP * e;
+            if (k <= N / 2) {
+                cpx<T> w = z[e];
+                if (k == 0 || k == N / 2) w.y = T(0);
+                dst[(long long)k * a.inner] = w;
+            }
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// 1D: one workgroup per field, everything in LDS/registers
+// ---------------------------------------------------------------------------
+template <typename T>
+struct Args1D {
+    const T* u_in;          // apply: input fields; step: u
+    const T* v_in;
+    T* u_out;               // apply: out; step: u
+    T* v_out;
+    int N;
+    const double* mu2;      // axis table
+    const cpx<T>* tw;
+    const double* delta;    // per point (stride coef_stride per item)
+    const T* A;
+    const T* B;
+    long long coef_stride;
+    const SolveScalars* sc;
+    int sc_stride;
+    int M, op, nsteps, model;
+    double dt, invN;
+    int* flag;
+};
+
+template <typename T, int N, int E>
+__global__ __launch_bounds__(N / E) void k_1d_apply(Args1D<T> a) {
+    constexpr int TP = N / E;
+    __shared__ cpx<T> lds_raw[LdsPencil<T>::footprint(N)];
+    const LdsPencil<T> lds{lds_raw};
+    const int t = threadIdx.x;
+    const int item = blockIdx.x;
+    const SolveScalars sc = a.sc[item * a.sc_stride];
+    const T* u = a.u_in + (long long)item * N;
+    cpx<T> x[E];
+#pragma unroll
+    for (int e = 0; e < E; ++e) x[e] = {u[t + TP * e], T(0)};
+    fft_pencil<T, N, E, -1>(x, t, lds, a.tw);
+    const double sig = (a.op == 2) ? sc.sig2 : sc.sig1;
+    cpx<double> r[E];
+    double L[E], dl[E], acc[E], dp[E];
+    const double* dd = a.delta + (long long)item * a.coef_stride;
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+        const double m2 = a.mu2[t + TP * e];
+        double P = 0.0;
+        L[e] = 0.0;
+        if (m2 > 0.0) {
+            L[e] = log(m2);
+            P = exp(sig * L[e]);
+        }
+        r[e] = {P * double(x[e].x) * a.invN, P * double(x[e].y) * a.invN};
+        dl[e] = dd[t + TP * e];
+        acc[e] = 0.0;
+        dp[e] = 1.0;
+    }
+    for (int m = 0; m <= a.M; m += 2) {
+        const bool pair = (m + 1 <= a.M);
+        cpx<T> y[E];
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+            const cpx<double> x0 = r[e];
+            const double f = L[e] / double(m + 1);
+            const cpx<double> x1 = pair ? cpx<double>{x0.x * f, x0.y * f} : cpx<double>{0.0, 0.0};
+            y[e] = {T(x0.x - x1.y), T(x0.y + x1.x)};
+            const double g = pair ? L[e] / double(m + 2) : 0.0;
+            r[e] = {x1.x * g, x1.y * g};
+        }
+        fft_pencil<T, N, E, +1>(y, t, lds, a.tw);
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+            acc[e] += dp[e] * (double(y[e].x) + dl[e] * double(y[e].y));
+            dp[e] *= dl[e] * dl[e];
+        }
+    }
+    T* o = a.u_out + (long long)item * N;
+#pragma unroll
+    for (int e = 0; e < E; ++e) o[t + TP * e] = T(acc[e]);
+}
+
+// Symbols of one mode: ln|mu|^2 and |mu|^{2 sig1}, |mu|^{2 sig2} (zero at k = 0).
+__device__ __forceinline__ void mode_symbols(double m2, double sig1, double sig2, double& L,
+                                             double& P1, double& P2) {
+    L = 0.0;
+    P1 = 0.0;
+    P2 = 0.0;
+    if (m2 > 0.0) {
+        L = log(m2);
+        P1 = exp(sig1 * L);
+        P2 = exp(sig2 * L);
+    }
+}
+
+template <typename T, int N, int E>
+__global__ __launch_bounds__(N / E) void k_1d_step(Args1D<T> a) {
+    constexpr int TP = N / E;
+    __shared__ cpx<T> lds_raw[LdsPencil<T>::footprint(N)];
+    const LdsPencil<T> lds{lds_raw};
+    const int t = threadIdx.x;
+    const int item = blockIdx.x;
+    const SolveScalars sc = a.sc[item * a.sc_stride];
+    const long long co = (long long)item * a.coef_stride;
+    cpx<double> uh[E], vh[E];
+    {
+        cpx<T> x[E];
+        const T* u = a.u_in + (long long)item * N;
+#pragma unroll
+        for (int e = 0; e < E; ++e) x[e] = {u[t + TP * e], T(0)};
+        fft_pencil<T, N, E, -1>(x, t, lds, a.tw);
+#pragma unroll
+        for (int e = 0; e < E; ++e) uh[e] = {double(x[e].x) * a.invN, double(x[e].y) * a.invN};
+        const T* v = a.v_in + (long long)item * N;
+#pragma unroll
+        for (int e = 0; e < E; ++e) x[e] = {v[t + TP * e], T(0)};
+        fft_pencil<T, N, E, -1>(x, t, lds, a.tw);
+#pragma unroll
+        for (int e = 0; e < E; ++e) vh[e] = {double(x[e].x) * a.invN, double(x[e].y) * a.invN};
+    }
+    auto propagate = [&](double tp) {
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+            double L, P1, P2, g11, g12, g21, g22;
+            mode_symbols(a.mu2[t + TP * e], sc.sig1, sc.sig2, L, P1, P2);
+            damped_flow(P1, P2, sc.kappa0, sc.beta0, tp, g11, g12, g21, g22);
+            const cpx<double> u0 = uh[e], v0 = vh[e];
+            uh[e] = {g11 * u0.x + g12 * v0.x, g11 * u0.y + g12 * v0.y};
+            vh[e] = {g21 * u0.x + g22 * v0.x, g21 * u0.y + g22 * v0.y};
+        }
+    };
+    bool bad = false;
+    if (a.nsteps > 0) propagate(0.5 * a.dt);
+    for (int s = 0; s < a.nsteps; ++s) {
+        double acc[E];
+        if (a.model == MODEL_GENERIC) {
+            // dv = -kappa sum_{s=1..M} delta^s t_s + lambda u^3, with t_s from
+            // l_s |mu|^{2 s0} u_hat (s <= M) and u from u_hat (s = M+1), two per transform
+            double uu[E];
+#pragma unroll
+            for (int e = 0; e < E; ++e) {
+                acc[e] = 0.0;
+                uu[e] = 0.0;
+            }
+            const int ns = a.M + 2;
+            for (int s0 = 0; s0 < ns; s0 += 2) {
+                cpx<T> y[E];
+#pragma unroll
+                for (int e = 0; e < E; ++e) {
+                    double L, P1, P2;
+                    mode_symbols(a.mu2[t + TP * e], sc.sig1, sc.sig2, L, P1, P2);
+                    cpx<double> xs[2];
+                    for (int h = 0; h < 2; ++h) {
+                        const int sidx = s0 + h;
+                        double c = 0.0;
+                        if (sidx <= a.M) {
+                            c = P1;
+                            for (int j = 1; j <= sidx; ++j) c *= L / double(j);
+                        } else if (sidx == a.M + 1) {
+                            c = 1.0;
+                        }
+                        xs[h] = {c * uh[e].x, c * uh[e].y};
+                    }
+                    y[e] = {T(xs[0].x - xs[1].y), T(xs[0].y + xs[1].x)};
+                }
+                fft_pencil<T, N, E, +1>(y, t, lds, a.tw);
+#pragma unroll
+                for (int e = 0; e < E; ++e) {
+                    const int k = t + TP * e;
+                    const double d = a.delta[co + k];
+                    for (int h = 0; h < 2; ++h) {
+                        const int sidx = s0 + h;
+                        const double val = h == 0 ? double(y[e].x) : double(y[e].y);
+                        if (sidx == a.M + 1) {
+                            uu[e] = val;
+                        } else if (sidx > 0 && sidx <= a.M) {
+                            double dm = 1.0;
+                            for (int j = 0; j < sidx; ++j) dm *= d;
+                            acc[e] -= sc.kappa0 * dm * val;
+                        }
+                    }
+                }
+            }
+#pragma unroll
+            for (int e = 0; e < E; ++e) acc[e] += sc.lambda * uu[e] * uu[e] * uu[e];
+        } else {
+            // kick: dv = (kappa0 - A) t1_0 + (beta0 - B) t2_0 + sum_{m>=1} delta^m (-A t1_m - B t2_m)
+            cpx<T> y[E];
+            {
+#pragma unroll
+                for (int e = 0; e < E; ++e) {
+                    double L, P1, P2;
+                    mode_symbols(a.mu2[t + TP * e], sc.sig1, sc.sig2, L, P1, P2);
+                    // m = 0 pair: |mu|^{2 sig1} u_hat + i |mu|^{2 sig2} v_hat
+                    y[e] = {T(P1 * uh[e].x - P2 * vh[e].y), T(P1 * uh[e].y + P2 * vh[e].x)};
+                    acc[e] = 0.0;
+                }
+            }
+            double lm = 1.0;  // running 1/m! for the multipliers
+            for (int m = 0; m <= a.M; ++m) {
+                fft_pencil<T, N, E, +1>(y, t, lds, a.tw);
+                const double k0c = (m == 0) ? sc.kappa0 : 0.0;
+                const double b0c = (m == 0) ? sc.beta0 : 0.0;
+#pragma unroll
+                for (int e = 0; e < E; ++e) {
+                    const int k = t + TP * e;
+                    const double d = a.delta[co + k];
+                    double dm = 1.0;
+                    for (int j = 0; j < m; ++j) dm *= d;
+                    const double ca = -double(a.A[co + k]) * dm;
+                    const double cb = -double(a.B[co + k]) * dm;
+                    acc[e] += (k0c + ca) * double(y[e].x) + (b0c + cb) * double(y[e].y);
+                }
+                if (m < a.M) {
+                    lm /= double(m + 1);
+#pragma unroll
+                    for (int e = 0; e < E; ++e) {
+                        double L, P1, P2;
+                        mode_symbols(a.mu2[t + TP * e], sc.sig1, sc.sig2, L, P1, P2);
+                        double lp = lm;
+                        for (int j = 0; j <= m; ++j) lp *= L;
+                        const double c1 = lp * P1, c2 = lp * P2;
+                        y[e] = {T(c1 * uh[e].x - c2 * vh[e].y), T(c1 * uh[e].y + c2 * vh[e].x)};
+                    }
+                }
+            }
+        }
+        cpx<T> z[E];
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+            bad |= !isfinite(acc[e]);
+            z[e] = {T(acc[e]), T(0)};
+        }
+        fft_pencil<T, N, E, -1>(z, t, lds, a.tw);
+        const double sc2 = a.dt * a.invN;
+#pragma unroll
+        for (int e = 0; e < E; ++e) vh[e] = {vh[e].x + sc2 * double(z[e].x), vh[e].y + sc2 * double(z[e].y)};
+        propagate(s + 1 < a.nsteps ? a.dt : 0.5 * a.dt);
+    }
+    if (bad) a.flag[0] = 1;
+    cpx<T> y[E];
+#pragma unroll
+    for (int e = 0; e < E; ++e) y[e] = {T(uh[e].x - vh[e].y), T(uh[e].y + vh[e].x)};
+    fft_pencil<T, N, E, +1>(y, t, lds, a.tw);
+    T* uo = a.u_out + (long long)item * N;
+    T* vo = a.v_out + (long long)item * N;
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+        uo[t + TP * e] = y[e].x;
+        vo[t + TP * e] = y[e].y;
+    }
+}
+
+}  // namespace vofl

@@ -1,0 +1,38 @@
+// Host-side launchers: map a runtime transform length onto the compiled
+// kernel instantiations (kernels_f32.hip, kernels_f64.hip).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "kernels.hpp"
+
+namespace vofl {
+
+// Elements per thread of each kernel class for a transform length N.
+constexpr int e_contig(int N) { return N < 8 ? N : 8; }
+constexpr int e_mid(int N) { return N < 16 ? N : 16; }
+constexpr int e_r2c0(int N) { return N < 16 ? N : 16; }
+// 1D: one workgroup of at most 512 threads per field
+constexpr int e_1d(int N) { return N < 4 ? N : (N <= 2048 ? 4 : 8); }
+constexpr int e_c2r0(int N) { return N < 8 ? N : 8; }
+// pencils per workgroup of k_contig: about 256 threads
+constexpr int p_contig(int N) { return (256 / (N / e_contig(N))) > 0 ? (256 / (N / e_contig(N))) : 1; }
+
+template <typename T>
+struct Launch {
+    static bool supported_multi(int N);
+    static bool supported_1d(int N);
+    static int tile_w(int N);
+    static int c2r_w(int N);
+    static hipError_t contig(int N, const ContigArgs<T>& a, int items, hipStream_t s);
+    static hipError_t mid(int N, int dir, const MidArgs<T>& a, int planes, int items, hipStream_t s);
+    static hipError_t r2c0(int N, const R2CArgs<T>& a, int items, hipStream_t s);
+    static hipError_t c2r0(int N, const C2RArgs<T>& a, int items, hipStream_t s);
+    static hipError_t d1_apply(int N, const Args1D<T>& a, int items, hipStream_t s);
+    static hipError_t d1_step(int N, const Args1D<T>& a, int items, hipStream_t s);
+};
+
+extern template struct Launch<float>;
+extern template struct Launch<double>;
+
+}  // namespace vofl

@@ -1,0 +1,149 @@
+// Definitions of the launchers, included once per precision.
+#pragma once
+
+#include "launch.hpp"
+
+namespace vofl {
+
+#define VOFL_MULTI_SIZES(X) X(8) X(16) X(32) X(64) X(128) X(256) X(512) X(1024)
+#define VOFL_1D_SIZES(X) X(8) X(16) X(32) X(64) X(128) X(256) X(512) X(1024) X(2048) X(4096)
+
+template <typename T>
+bool Launch<T>::supported_multi(int N) {
+    switch (N) {
+#define C_(n) case n:
+        VOFL_MULTI_SIZES(C_)
+#undef C_
+        return true;
+        default: return false;
+    }
+}
+
+template <typename T>
+bool Launch<T>::supported_1d(int N) {
+    switch (N) {
+#define C_(n) case n:
+        VOFL_1D_SIZES(C_)
+#undef C_
+        return true;
+        default: return false;
+    }
+}
+
+template <typename T>
+int Launch<T>::tile_w(int N) {
+    switch (N) {
+#define C_(n) case n: return tile_width<T, n>();
+        VOFL_MULTI_SIZES(C_)
+#undef C_
+        default: return 0;
+    }
+}
+
+template <typename T>
+int Launch<T>::c2r_w(int N) {
+    switch (N) {
+#define C_(n) case n: return c2r_width<T, n>();
+        VOFL_MULTI_SIZES(C_)
+#undef C_
+        default: return 0;
+    }
+}
+
+template <typename T>
+hipError_t Launch<T>::contig(int N, const ContigArgs<T>& a, int items, hipStream_t s) {
+    switch (N) {
+#define C_(n)                                                                           \
+    case n: {                                                                           \
+        constexpr int E = e_contig(n), P = p_contig(n);                                 \
+        dim3 grid((a.npencils + P - 1) / P, items);                                     \
+        k_contig<T, n, E, P><<<grid, dim3(P * (n / E)), 0, s>>>(a);                     \
+        return hipGetLastError();                                                       \
+    }
+        VOFL_MULTI_SIZES(C_)
+#undef C_
+        default: return hipErrorInvalidValue;
+    }
+}
+
+template <typename T>
+hipError_t Launch<T>::mid(int N, int dir, const MidArgs<T>& a, int planes, int items,
+                          hipStream_t s) {
+    switch (N) {
+#define C_(n)                                                                           \
+    case n: {                                                                           \
+        constexpr int E = e_mid(n), W = tile_width<T, n>();                             \
+        dim3 grid(planes * a.tiles_per_plane, items * a.nf);                            \
+        if (dir < 0) k_mid<T, n, E, W, -1><<<grid, dim3(W * (n / E)), 0, s>>>(a);       \
+        else k_mid<T, n, E, W, +1><<<grid, dim3(W * (n / E)), 0, s>>>(a);              \
+        return hipGetLastError();                                                       \
+    }
+        VOFL_MULTI_SIZES(C_)
+#undef C_
+        default: return hipErrorInvalidValue;
+    }
+}
+
+template <typename T>
+hipError_t Launch<T>::r2c0(int N, const R2CArgs<T>& a, int items, hipStream_t s) {
+    switch (N) {
+#define C_(n)                                                                           \
+    case n: {                                                                           \
+        constexpr int E = e_r2c0(n), W = tile_width<T, n>();                            \
+        dim3 grid((a.inner + W - 1) / W, items * a.nf);                                 \
+        k_r2c0<T, n, E, W><<<grid, dim3(W * (n / E)), 0, s>>>(a);                       \
+        return hipGetLastError();                                                       \
+    }
+        VOFL_MULTI_SIZES(C_)
+#undef C_
+        default: return hipErrorInvalidValue;
+    }
+}
+
+template <typename T>
+hipError_t Launch<T>::c2r0(int N, const C2RArgs<T>& a, int items, hipStream_t s) {
+    switch (N) {
+#define C_(n)                                                                           \
+    case n: {                                                                           \
+        constexpr int W = c2r_width<T, n>(), E = e_c2r0(n);                                   \
+        dim3 grid((a.inner + W - 1) / W, items);                                        \
+        k_c2r0<T, n, E, W><<<grid, dim3(W * (n / E)), 0, s>>>(a);                       \
+        return hipGetLastError();                                                       \
+    }
+        VOFL_MULTI_SIZES(C_)
+#undef C_
+        default: return hipErrorInvalidValue;
+    }
+}
+
+template <typename T>
+hipError_t Launch<T>::d1_apply(int N, const Args1D<T>& a, int items, hipStream_t s) {
+    switch (N) {
+#define C_(n)                                                                           \
+    case n: {                                                                           \
+        constexpr int E = e_1d(n);                                                      \
+        k_1d_apply<T, n, E><<<dim3(items), dim3(n / E), 0, s>>>(a);                     \
+        return hipGetLastError();                                                       \
+    }
+        VOFL_1D_SIZES(C_)
+#undef C_
+        default: return hipErrorInvalidValue;
+    }
+}
+
+template <typename T>
+hipError_t Launch<T>::d1_step(int N, const Args1D<T>& a, int items, hipStream_t s) {
+    switch (N) {
+#define C_(n)                                                                           \
+    case n: {                                                                           \
+        constexpr int E = e_1d(n);                                                      \
+        k_1d_step<T, n, E><<<dim3(items), dim3(n / E), 0, s>>>(a);                      \
+        return hipGetLastError();                                                       \
+    }
+        VOFL_1D_SIZES(C_)
+#undef C_
+        default: return hipErrorInvalidValue;
+    }
+}
+
+}  // namespace vofl

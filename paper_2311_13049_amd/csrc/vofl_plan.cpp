@@ -1,0 +1,772 @@
+// libvofl host side: descriptor validation, FP64 plan tables, device
+// workspace, and the launch sequences of vofl_apply / vofl_step.
+//
+// Launch sequences (2D/3D; axis 0 is the half-spectrum axis, the last axis is
+// contiguous; the 3D middle axis is transformed by k_mid):
+//   apply (2.13): r2c0(u) -> [mid fwd] -> contig(1/N, |mu|^{2 s0} l_m, inverse
+//                 last axis, m = 0..M) -> [mid inv] -> c2r0(sum_m delta^m t_m)
+//   step (3.13):  r2c0(u), r2c0(v) -> [mid fwd] -> contig(state, G(dt/2), terms)
+//                 then per step: [mid inv] -> c2r0(kick rhs, forward axis 0)
+//                 -> [mid fwd] -> contig(v_hat += dt dv_hat, G(dt) or G(dt/2)
+//                 on the last step, next terms or export) ; finally
+//                 [mid inv] -> c2r0(export u, v).
+// 1D runs one workgroup per field with the whole loop in one kernel.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <string>
+#include <vector>
+
+#include "launch.hpp"
+#include "vofl.h"
+
+using namespace vofl;
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const char* fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return code;
+}
+
+int hip_fail(hipError_t e, const char* what) {
+    return fail(VOFL_ERR_DEVICE, "%s: %s", what, hipGetErrorString(e));
+}
+
+// Sizes derived from a validated descriptor (no device access).
+struct Geometry {
+    int ndim = 0;
+    int n[3] = {1, 1, 1};
+    long long Nreal = 0;   // points of one field
+    int n0h = 0;           // n0/2 + 1
+    long long H = 0;       // complex elements of one half spectrum (2D/3D)
+    int inner = 0;         // columns of the axis-0 transform
+    int nlast = 0;         // last-axis length
+    int npencils = 0;      // last-axis pencils of one half spectrum
+    int batch = 1, max_batch = 1, ncoef = 1;
+    int nterm = 0;         // term slots of one step
+    int step_slots = 0, apply_slots = 0;
+    size_t elt = 0;        // bytes of one working-precision real
+    size_t bytes = 0;      // total device bytes
+};
+
+bool is_fp32(const vofl_desc* d) { return d->precision == VOFL_FP32; }
+
+bool supported_len(int ndim, int n, bool fp32) {
+    if (ndim == 1) return fp32 ? Launch<float>::supported_1d(n) : Launch<double>::supported_1d(n);
+    return fp32 ? Launch<float>::supported_multi(n) : Launch<double>::supported_multi(n);
+}
+
+int derive(const vofl_desc* d, Geometry& g) {
+    if (!d) return fail(VOFL_ERR_INVALID, "desc is NULL");
+    if (d->ndim < 1 || d->ndim > 3) return fail(VOFL_ERR_INVALID, "ndim must be 1, 2 or 3 (got %d)", d->ndim);
+    if (d->precision != VOFL_FP64 && d->precision != VOFL_FP32)
+        return fail(VOFL_ERR_INVALID, "precision must be VOFL_FP64 or VOFL_FP32");
+    if (d->model != VOFL_MODEL_SEISMIC && d->model != VOFL_MODEL_GENERIC)
+        return fail(VOFL_ERR_INVALID, "unknown model %d", d->model);
+    g.ndim = d->ndim;
+    g.Nreal = 1;
+    for (int i = 0; i < d->ndim; ++i) {
+        const int n = d->n[i];
+        if (n < 2 || n % 2) return fail(VOFL_ERR_INVALID, "n[%d] = %d must be even and >= 2", i, n);
+        if (!(std::isfinite(d->lo[i]) && std::isfinite(d->hi[i]) && d->hi[i] > d->lo[i]))
+            return fail(VOFL_ERR_INVALID, "box axis %d must satisfy lo < hi (finite)", i);
+        if (!supported_len(d->ndim, n, is_fp32(d)))
+            return fail(VOFL_ERR_UNSUPPORTED, "no compiled transform of length %d (axis %d)", n, i);
+        g.n[i] = n;
+        g.Nreal *= n;
+    }
+    if (g.Nreal > (1LL << 31)) return fail(VOFL_ERR_INVALID, "grid too large");
+    if (d->M < 0 || d->M > 64) return fail(VOFL_ERR_INVALID, "M must be in [0, 64] (got %d)", d->M);
+    if (!(std::isfinite(d->dt) && d->dt > 0)) return fail(VOFL_ERR_INVALID, "dt must be finite and > 0");
+    if (d->max_batch < 0 || d->max_batch > 4096) return fail(VOFL_ERR_INVALID, "max_batch out of range");
+    if (d->batch < 0 || d->batch > 4096) return fail(VOFL_ERR_INVALID, "batch out of range");
+    if (d->coef_per_solve != 0 && d->coef_per_solve != 1)
+        return fail(VOFL_ERR_INVALID, "coef_per_solve must be 0 or 1");
+    g.batch = d->batch ? d->batch : 1;
+    g.max_batch = d->max_batch ? d->max_batch : 1;
+    g.ncoef = d->coef_per_solve ? g.batch : 1;
+    const long long ncv = (long long)g.ncoef * g.Nreal;
+    if (d->model == VOFL_MODEL_SEISMIC) {
+        if (!(std::isfinite(d->c0) && d->c0 > 0 && std::isfinite(d->omega0) && d->omega0 > 0))
+            return fail(VOFL_ERR_INVALID, "c0 and omega0 must be finite and > 0");
+        if ((d->Q == nullptr) == (d->gamma == nullptr))
+            return fail(VOFL_ERR_INVALID, "give exactly one of Q and gamma");
+        if (d->Q) {
+            for (long long i = 0; i < ncv; ++i) {
+                const double q = d->Q[i];
+                if (!(q > 0)) return fail(VOFL_ERR_INVALID, "Q[%lld] = %g must be > 0", i, q);
+            }
+        } else {
+            for (long long i = 0; i < ncv; ++i) {
+                const double gm = d->gamma[i];
+                if (!(std::isfinite(gm) && gm >= 0 && gm < 0.5))
+                    return fail(VOFL_ERR_INVALID, "gamma[%lld] = %g must be in [0, 1/2)", i, gm);
+            }
+        }
+    } else {
+        if (!d->s) return fail(VOFL_ERR_INVALID, "generic model needs s");
+        if (!(std::isfinite(d->kappa) && d->kappa > 0)) return fail(VOFL_ERR_INVALID, "kappa must be > 0");
+        if (!std::isfinite(d->lambda)) return fail(VOFL_ERR_INVALID, "lambda must be finite");
+        for (long long i = 0; i < ncv; ++i) {
+            const double sv = d->s[i];
+            if (!(std::isfinite(sv) && sv > 0 && sv < 2))
+                return fail(VOFL_ERR_INVALID, "s[%lld] = %g must be in (0, 2)", i, sv);
+        }
+    }
+    g.elt = is_fp32(d) ? 4 : 8;
+    const size_t celt = 2 * g.elt;
+    size_t bytes = 0;
+    // per-axis tables: twiddles (working precision) and mu^2 (FP64)
+    for (int i = 0; i < d->ndim; ++i) bytes += g.n[i] * (celt + 8);
+    // per-point coefficients: delta (FP64), A and B (working precision), scalars
+    bytes += (size_t)ncv * (8 + 2 * g.elt) + (size_t)g.ncoef * sizeof(SolveScalars) + 256;
+    if (d->ndim >= 2) {
+        g.n0h = g.n[0] / 2 + 1;
+        g.nlast = g.n[d->ndim - 1];
+        g.inner = (int)(g.Nreal / g.n[0]);
+        g.H = (long long)g.n0h * g.inner;
+        g.npencils = (int)(g.H / g.nlast);
+        g.nterm = (d->model == VOFL_MODEL_SEISMIC) ? 2 * (d->M + 1) : d->M + 2;
+        g.step_slots = g.nterm + 3;
+        g.apply_slots = d->M + 2;
+        const long long slots =
+            std::max((long long)g.batch * g.step_slots, (long long)g.max_batch * g.apply_slots);
+        if ((long long)g.batch * g.step_slots > 65535 || (long long)g.max_batch * g.apply_slots > 65535)
+            return fail(VOFL_ERR_INVALID, "batch x slots exceeds the launch grid limit");
+        bytes += (size_t)slots * g.H * celt;                  // work slots
+        bytes += (size_t)2 * g.batch * g.H * 16;              // FP64 spectral state
+    }
+    g.bytes = bytes;
+    if (d->hbm_budget && bytes > d->hbm_budget)
+        return fail(VOFL_ERR_NOMEM, "plan needs %zu bytes, above hbm_budget %zu", bytes, d->hbm_budget);
+    return VOFL_OK;
+}
+
+// Coefficients (1.1): c = c0 cos(pi g/2), eta = -c0^{2g} w0^{-2g} cos(pi g),
+// tau = -c0^{2g-1} w0^{-2g} sin(pi g); A = -c^2 eta, B = -c^2 tau.
+void seismic_AB(double g, double c0, double w0, double& A, double& B) {
+    const double c = c0 * std::cos(M_PI * g / 2.0);
+    const double eta = -std::pow(c0, 2.0 * g) * std::pow(w0, -2.0 * g) * std::cos(M_PI * g);
+    const double tau = -std::pow(c0, 2.0 * g - 1.0) * std::pow(w0, -2.0 * g) * std::sin(M_PI * g);
+    A = -c * c * eta;
+    B = -c * c * tau;
+}
+
+struct TimedRec {
+    int cls;
+    hipEvent_t a, b;
+};
+
+}  // namespace
+
+struct vofl_plan_s {
+    Geometry g;
+    int model = 0, precision = 0, M = 0;
+    double dt = 0;
+    double lo[3] = {0, 0, 0}, hi[3] = {0, 0, 0};
+    std::vector<SolveScalars> sc_host;
+    // device memory
+    double* mu2[3] = {nullptr, nullptr, nullptr};
+    void* tw[3] = {nullptr, nullptr, nullptr};
+    double* delta = nullptr;
+    void* A = nullptr;
+    void* B = nullptr;
+    SolveScalars* sc = nullptr;
+    void* U = nullptr;
+    void* V = nullptr;
+    void* work = nullptr;
+    int* flag = nullptr;
+    std::vector<void*> allocs;
+    hipStream_t own_stream = nullptr;  // used by vofl_step_batch
+    hipEvent_t fork_ev = nullptr, join_ev = nullptr;
+    // timing
+    bool timing = false;
+    std::vector<TimedRec> pending;
+    std::vector<hipEvent_t> pool;
+    std::vector<std::string> cls_names;
+    std::map<int, std::pair<double, long long>> totals;
+
+    ~vofl_plan_s() {
+        for (auto& r : pending) {
+            pool.push_back(r.a);
+            pool.push_back(r.b);
+        }
+        for (auto e : pool) (void)hipEventDestroy(e);
+        if (fork_ev) (void)hipEventDestroy(fork_ev);
+        if (join_ev) (void)hipEventDestroy(join_ev);
+        if (own_stream) (void)hipStreamDestroy(own_stream);
+        for (void* p : allocs) (void)hipFree(p);
+    }
+
+    int cls_id(const char* name) {
+        for (size_t i = 0; i < cls_names.size(); ++i)
+            if (cls_names[i] == name) return (int)i;
+        cls_names.emplace_back(name);
+        return (int)cls_names.size() - 1;
+    }
+    hipEvent_t get_event() {
+        if (!pool.empty()) {
+            hipEvent_t e = pool.back();
+            pool.pop_back();
+            return e;
+        }
+        hipEvent_t e = nullptr;
+        (void)hipEventCreate(&e);
+        return e;
+    }
+    // wrap one launch: returns the launch status
+    template <class F>
+    hipError_t timed(const char* name, hipStream_t s, F&& launch) {
+        if (!timing) return launch();
+        TimedRec r{cls_id(name), get_event(), get_event()};
+        (void)hipEventRecord(r.a, s);
+        hipError_t e = launch();
+        (void)hipEventRecord(r.b, s);
+        pending.push_back(r);
+        return e;
+    }
+    void drain_timing() {
+        for (auto& r : pending) {
+            (void)hipEventSynchronize(r.b);
+            float ms = 0.f;
+            (void)hipEventElapsedTime(&ms, r.a, r.b);
+            auto& t = totals[r.cls];
+            t.first += ms;
+            t.second += 1;
+            pool.push_back(r.a);
+            pool.push_back(r.b);
+        }
+        pending.clear();
+    }
+};
+
+namespace {
+
+template <typename P>
+int dalloc(vofl_plan_s* p, P** ptr, size_t bytes) {
+    void* q = nullptr;
+    hipError_t e = hipMalloc(&q, bytes ? bytes : 16);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(VOFL_ERR_NOMEM, "hipMalloc(%zu): %s", bytes, hipGetErrorString(e));
+    }
+    p->allocs.push_back(q);
+    *ptr = static_cast<P*>(q);
+    return VOFL_OK;
+}
+
+template <typename T>
+int upload_tables(vofl_plan_s* p, const std::vector<double>& delta, const std::vector<double>& A,
+                  const std::vector<double>& B) {
+    const Geometry& g = p->g;
+    for (int ax = 0; ax < g.ndim; ++ax) {
+        const int n = g.n[ax];
+        std::vector<cpx<T>> tw(n);
+        std::vector<double> mu2(n);
+        const double L = p->hi[ax] - p->lo[ax];
+        for (int j = 0; j < n; ++j) {
+            const double ang = 2.0 * M_PI * (double)j / (double)n;
+            tw[j] = {T(std::cos(ang)), T(-std::sin(ang))};
+            const int k = (j < n / 2) ? j : j - n;  // bin j holds wavenumber k (eq. (2.2))
+            const double mu = 2.0 * M_PI * (double)k / L;
+            mu2[j] = mu * mu;
+        }
+        int rc;
+        if ((rc = dalloc(p, (cpx<T>**)&p->tw[ax], n * sizeof(cpx<T>)))) return rc;
+        if ((rc = dalloc(p, &p->mu2[ax], n * sizeof(double)))) return rc;
+        hipError_t e = hipMemcpy(p->tw[ax], tw.data(), n * sizeof(cpx<T>), hipMemcpyHostToDevice);
+        if (e == hipSuccess) e = hipMemcpy(p->mu2[ax], mu2.data(), n * sizeof(double), hipMemcpyHostToDevice);
+        if (e != hipSuccess) return hip_fail(e, "table upload");
+    }
+    const size_t ncv = delta.size();
+    std::vector<T> At(ncv), Bt(ncv);
+    for (size_t i = 0; i < ncv; ++i) {
+        At[i] = T(A[i]);
+        Bt[i] = T(B[i]);
+    }
+    int rc;
+    if ((rc = dalloc(p, &p->delta, ncv * sizeof(double)))) return rc;
+    if ((rc = dalloc(p, (T**)&p->A, ncv * sizeof(T)))) return rc;
+    if ((rc = dalloc(p, (T**)&p->B, ncv * sizeof(T)))) return rc;
+    if ((rc = dalloc(p, &p->sc, p->sc_host.size() * sizeof(SolveScalars)))) return rc;
+    if ((rc = dalloc(p, &p->flag, 256))) return rc;
+    hipError_t e = hipMemcpy(p->delta, delta.data(), ncv * sizeof(double), hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(p->A, At.data(), ncv * sizeof(T), hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(p->B, Bt.data(), ncv * sizeof(T), hipMemcpyHostToDevice);
+    if (e == hipSuccess)
+        e = hipMemcpy(p->sc, p->sc_host.data(), p->sc_host.size() * sizeof(SolveScalars), hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemset(p->flag, 0, 256);
+    if (e != hipSuccess) return hip_fail(e, "coefficient upload");
+    if (g.ndim >= 2) {
+        const long long slots = std::max((long long)g.batch * g.step_slots, (long long)g.max_batch * g.apply_slots);
+        if ((rc = dalloc(p, (cpx<T>**)&p->work, (size_t)slots * g.H * sizeof(cpx<T>)))) return rc;
+        if ((rc = dalloc(p, (cpx<double>**)&p->U, (size_t)g.batch * g.H * sizeof(cpx<double>)))) return rc;
+        if ((rc = dalloc(p, (cpx<double>**)&p->V, (size_t)g.batch * g.H * sizeof(cpx<double>)))) return rc;
+    }
+    return VOFL_OK;
+}
+
+// ---------------------------------------------------------------------------
+// launch sequences
+// ---------------------------------------------------------------------------
+
+template <typename T>
+ContigArgs<T> contig_base(vofl_plan_s* p) {
+    const Geometry& g = p->g;
+    ContigArgs<T> a{};
+    a.H = g.H;
+    a.npencils = g.npencils;
+    a.n1 = (g.ndim == 3) ? g.n[1] : 1;
+    a.mu2_0 = p->mu2[0];
+    a.mu2_1 = (g.ndim == 3) ? p->mu2[1] : nullptr;
+    a.mu2_l = p->mu2[g.ndim - 1];
+    a.tw = (const cpx<T>*)p->tw[g.ndim - 1];
+    a.sc = p->sc;
+    a.sc_stride = g.ncoef > 1 ? 1 : 0;
+    a.U = (cpx<double>*)p->U;
+    a.V = (cpx<double>*)p->V;
+    a.M = p->M;
+    a.dt = p->dt;
+    a.invN = 1.0 / (double)g.Nreal;
+    return a;
+}
+
+template <typename T>
+hipError_t mid(vofl_plan_s* p, int dir, int slots, int slot0, int nf, int items, hipStream_t s) {
+    const Geometry& g = p->g;
+    if (g.ndim != 3) return hipSuccess;
+    MidArgs<T> m{};
+    m.buf = (cpx<T>*)p->work;
+    m.slots = slots;
+    m.slot0 = slot0;
+    m.nf = nf;
+    m.H = g.H;
+    m.n2 = g.n[2];
+    const int W = Launch<T>::tile_w(g.n[1]);
+    m.tiles_per_plane = (g.n[2] + W - 1) / W;
+    m.tw = (const cpx<T>*)p->tw[1];
+    return p->timed("mid", s, [&] { return Launch<T>::mid(g.n[1], dir, m, g.n0h, items, s); });
+}
+
+template <typename T>
+C2RArgs<T> c2r_base(vofl_plan_s* p) {
+    const Geometry& g = p->g;
+    C2RArgs<T> c{};
+    c.H = g.H;
+    c.inner = g.inner;
+    c.tw = (const cpx<T>*)p->tw[0];
+    c.M = p->M;
+    c.model = p->model;
+    c.delta = p->delta;
+    c.A = (const T*)p->A;
+    c.B = (const T*)p->B;
+    c.coef_stride = g.ncoef > 1 ? g.Nreal : 0;
+    c.sc = p->sc;
+    c.sc_stride = g.ncoef > 1 ? 1 : 0;
+    c.Nreal = g.Nreal;
+    c.flag = p->flag;
+    return c;
+}
+
+template <typename T>
+int apply_multi(vofl_plan_s* p, int op, const T* u, T* out, int nf, hipStream_t s) {
+    const Geometry& g = p->g;
+    const int A = g.apply_slots, M = p->M;
+    cpx<T>* W = (cpx<T>*)p->work;
+    hipError_t e;
+    R2CArgs<T> r{};
+    r.in = u;
+    r.nf = 1;
+    r.Nreal = g.Nreal;
+    r.out = W;
+    r.slots = A;
+    r.slot0 = M + 1;
+    r.H = g.H;
+    r.inner = g.inner;
+    r.tw = (const cpx<T>*)p->tw[0];
+    e = p->timed("r2c0", s, [&] { return Launch<T>::r2c0(g.n[0], r, nf, s); });
+    if (e != hipSuccess) return hip_fail(e, "r2c0 launch");
+    if ((e = mid<T>(p, -1, A, M + 1, 1, nf, s)) != hipSuccess) return hip_fail(e, "mid launch");
+    ContigArgs<T> a = contig_base<T>(p);
+    a.in = W;
+    a.in_slots = A;
+    a.in_slot0 = M + 1;
+    a.nin = 1;
+    a.out = W;
+    a.out_slots = A;
+    a.out_slot0 = 0;
+    a.in_kind = IN_APPLY;
+    a.emit_kind = EMIT_APPLY;
+    a.do_prop = 0;
+    a.op = op;
+    e = p->timed("contig_apply", s, [&] { return Launch<T>::contig(g.nlast, a, nf, s); });
+    if (e != hipSuccess) return hip_fail(e, "contig launch");
+    if ((e = mid<T>(p, +1, A, 0, M + 1, nf, s)) != hipSuccess) return hip_fail(e, "mid launch");
+    C2RArgs<T> c = c2r_base<T>(p);
+    c.in = W;
+    c.slots = A;
+    c.mode = C2R_APPLY;
+    c.r0 = out;
+    e = p->timed("c2r0_apply", s, [&] { return Launch<T>::c2r0(g.n[0], c, nf, s); });
+    if (e != hipSuccess) return hip_fail(e, "c2r0 launch");
+    return VOFL_OK;
+}
+
+template <typename T>
+int step_multi(vofl_plan_s* p, T* u, T* v, int nsteps, hipStream_t s) {
+    if (nsteps == 0) return VOFL_OK;
+    const Geometry& g = p->g;
+    const int S = g.step_slots, nterm = g.nterm;
+    const int dv = nterm, h0 = nterm + 1;
+    const int items = g.batch;
+    const bool generic = p->model == VOFL_MODEL_GENERIC;
+    const int emit_terms = generic ? EMIT_GENERIC : EMIT_STEP;
+    cpx<T>* W = (cpx<T>*)p->work;
+    hipError_t e;
+
+    R2CArgs<T> r{};
+    r.nf = 1;
+    r.Nreal = g.Nreal;
+    r.out = W;
+    r.slots = S;
+    r.H = g.H;
+    r.inner = g.inner;
+    r.tw = (const cpx<T>*)p->tw[0];
+    r.in = u;
+    r.slot0 = h0;
+    e = p->timed("r2c0", s, [&] { return Launch<T>::r2c0(g.n[0], r, items, s); });
+    if (e != hipSuccess) return hip_fail(e, "r2c0 launch");
+    r.in = v;
+    r.slot0 = h0 + 1;
+    e = p->timed("r2c0", s, [&] { return Launch<T>::r2c0(g.n[0], r, items, s); });
+    if (e != hipSuccess) return hip_fail(e, "r2c0 launch");
+    if ((e = mid<T>(p, -1, S, h0, 2, items, s)) != hipSuccess) return hip_fail(e, "mid launch");
+
+    ContigArgs<T> a = contig_base<T>(p);
+    a.in = W;
+    a.in_slots = S;
+    a.in_slot0 = h0;
+    a.nin = 2;
+    a.out = W;
+    a.out_slots = S;
+    a.out_slot0 = 0;
+    a.in_kind = IN_INIT;
+    a.emit_kind = emit_terms;
+    a.do_prop = 1;
+    a.tprop = 0.5 * p->dt;
+    e = p->timed("contig_init", s, [&] { return Launch<T>::contig(g.nlast, a, items, s); });
+    if (e != hipSuccess) return hip_fail(e, "contig launch");
+
+    C2RArgs<T> c = c2r_base<T>(p);
+    c.in = W;
+    c.slots = S;
+    c.mode = generic ? C2R_KICK_GENERIC : C2R_KICK;
+    c.dv_out = W;
+    c.dv_slot = dv;
+
+    for (int st = 0; st < nsteps; ++st) {
+        const bool last = (st + 1 == nsteps);
+        if ((e = mid<T>(p, +1, S, 0, nterm, items, s)) != hipSuccess) return hip_fail(e, "mid launch");
+        e = p->timed("c2r0_kick", s, [&] { return Launch<T>::c2r0(g.n[0], c, items, s); });
+        if (e != hipSuccess) return hip_fail(e, "c2r0 launch");
+        if ((e = mid<T>(p, -1, S, dv, 1, items, s)) != hipSuccess) return hip_fail(e, "mid launch");
+        a.in_slot0 = dv;
+        a.nin = 1;
+        a.in_kind = IN_KICK;
+        a.tprop = last ? 0.5 * p->dt : p->dt;
+        a.emit_kind = last ? EMIT_EXPORT : emit_terms;
+        a.out_slot0 = last ? h0 : 0;
+        e = p->timed("contig_kick", s, [&] { return Launch<T>::contig(g.nlast, a, items, s); });
+        if (e != hipSuccess) return hip_fail(e, "contig launch");
+    }
+    if ((e = mid<T>(p, +1, S, h0, 2, items, s)) != hipSuccess) return hip_fail(e, "mid launch");
+    C2RArgs<T> x = c2r_base<T>(p);
+    x.in = W + (long long)h0 * g.H;
+    x.slots = S;
+    x.mode = C2R_EXPORT;
+    x.r0 = u;
+    x.r1 = v;
+    e = p->timed("c2r0_export", s, [&] { return Launch<T>::c2r0(g.n[0], x, items, s); });
+    if (e != hipSuccess) return hip_fail(e, "c2r0 launch");
+    return VOFL_OK;
+}
+
+template <typename T>
+Args1D<T> args_1d(vofl_plan_s* p) {
+    const Geometry& g = p->g;
+    Args1D<T> a{};
+    a.N = g.n[0];
+    a.mu2 = p->mu2[0];
+    a.tw = (const cpx<T>*)p->tw[0];
+    a.delta = p->delta;
+    a.A = (const T*)p->A;
+    a.B = (const T*)p->B;
+    a.coef_stride = g.ncoef > 1 ? g.Nreal : 0;
+    a.sc = p->sc;
+    a.sc_stride = g.ncoef > 1 ? 1 : 0;
+    a.M = p->M;
+    a.model = p->model;
+    a.dt = p->dt;
+    a.invN = 1.0 / (double)g.Nreal;
+    a.flag = p->flag;
+    return a;
+}
+
+template <typename T>
+int apply_any(vofl_plan_s* p, int op, const void* u, void* out, int nf, hipStream_t s) {
+    if (p->g.ndim >= 2) return apply_multi<T>(p, op, (const T*)u, (T*)out, nf, s);
+    Args1D<T> a = args_1d<T>(p);
+    a.u_in = (const T*)u;
+    a.u_out = (T*)out;
+    a.op = op;
+    hipError_t e = p->timed("1d_apply", s, [&] { return Launch<T>::d1_apply(a.N, a, nf, s); });
+    if (e != hipSuccess) return hip_fail(e, "1d apply launch");
+    return VOFL_OK;
+}
+
+template <typename T>
+int step_any(vofl_plan_s* p, void* u, void* v, int nsteps, hipStream_t s) {
+    if (p->g.ndim >= 2) return step_multi<T>(p, (T*)u, (T*)v, nsteps, s);
+    Args1D<T> a = args_1d<T>(p);
+    a.u_in = (const T*)u;
+    a.v_in = (const T*)v;
+    a.u_out = (T*)u;
+    a.v_out = (T*)v;
+    a.nsteps = nsteps;
+    hipError_t e = p->timed("1d_step", s, [&] { return Launch<T>::d1_step(a.N, a, p->g.batch, s); });
+    if (e != hipSuccess) return hip_fail(e, "1d step launch");
+    return VOFL_OK;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// C ABI
+// ---------------------------------------------------------------------------
+extern "C" {
+
+const char* vofl_last_error(void) { return g_err.c_str(); }
+
+const char* vofl_version(void) { return "vofl 0.1 (gfx950)"; }
+
+int vofl_plan_footprint(const vofl_desc* desc, size_t* bytes) {
+    Geometry g;
+    int rc = derive(desc, g);
+    if (rc) return rc;
+    if (!bytes) return fail(VOFL_ERR_INVALID, "bytes is NULL");
+    *bytes = g.bytes;
+    return VOFL_OK;
+}
+
+int vofl_plan(const vofl_desc* d, void* stream, vofl_plan_t* out) {
+    (void)stream;
+    if (!out) return fail(VOFL_ERR_INVALID, "out is NULL");
+    *out = nullptr;
+    Geometry g;
+    int rc = derive(d, g);
+    if (rc) return rc;
+    int ndev = 0;
+    hipError_t e = hipGetDeviceCount(&ndev);
+    if (e != hipSuccess || ndev < 1) {
+        (void)hipGetLastError();
+        return fail(VOFL_ERR_DEVICE, "no HIP device available");
+    }
+    // FP64 coefficient maps on the host (Section 1 coefficients of (1.1);
+    // grid means of gamma or s; delta = field - mean)
+    const long long N = g.Nreal;
+    const int ncoef = g.ncoef;
+    std::vector<double> delta((size_t)ncoef * N), A((size_t)ncoef * N), B((size_t)ncoef * N);
+    std::vector<SolveScalars> sc(ncoef);
+    for (int c = 0; c < ncoef; ++c) {
+        const long long off = (long long)c * N;
+        std::vector<double> f(N);
+        for (long long i = 0; i < N; ++i) {
+            if (d->model == VOFL_MODEL_GENERIC) f[i] = d->s[off + i];
+            else if (d->Q) f[i] = std::atan2(1.0, d->Q[off + i]) / M_PI;
+            else f[i] = d->gamma[off + i];
+        }
+        long double sum = 0.0L;
+        for (long long i = 0; i < N; ++i) sum += f[i];
+        const double mean = (double)(sum / (long double)N);
+        SolveScalars s{};
+        if (d->model == VOFL_MODEL_GENERIC) {
+            for (long long i = 0; i < N; ++i) {
+                delta[off + i] = f[i] - mean;
+                A[off + i] = d->kappa;
+                B[off + i] = 0.0;
+            }
+            s.sig1 = mean;
+            s.sig2 = 0.0;
+            s.kappa0 = d->kappa;
+            s.beta0 = 0.0;
+            s.lambda = d->lambda;
+        } else {
+            for (long long i = 0; i < N; ++i) {
+                delta[off + i] = f[i] - mean;
+                seismic_AB(f[i], d->c0, d->omega0, A[off + i], B[off + i]);
+            }
+            double k0, b0;
+            seismic_AB(mean, d->c0, d->omega0, k0, b0);
+            s.sig1 = 1.0 + mean;
+            s.sig2 = 0.5 + mean;
+            s.kappa0 = k0;
+            s.beta0 = b0;
+        }
+        sc[c] = s;
+    }
+    vofl_plan_s* p = new vofl_plan_s();
+    p->g = g;
+    p->model = d->model;
+    p->precision = d->precision;
+    p->M = d->M;
+    p->dt = d->dt;
+    for (int i = 0; i < 3; ++i) {
+        p->lo[i] = d->lo[i];
+        p->hi[i] = d->hi[i];
+    }
+    p->sc_host = sc;
+    rc = (d->precision == VOFL_FP32) ? upload_tables<float>(p, delta, A, B)
+                                     : upload_tables<double>(p, delta, A, B);
+    if (rc) {
+        delete p;
+        return rc;
+    }
+    *out = p;
+    return VOFL_OK;
+}
+
+int vofl_destroy(vofl_plan_t plan) {
+    if (!plan) return fail(VOFL_ERR_INVALID, "plan is NULL");
+    (void)hipDeviceSynchronize();
+    delete plan;
+    return VOFL_OK;
+}
+
+int vofl_apply(vofl_plan_t p, int op, const void* u, void* out, int nfields, void* stream) {
+    if (!p) return fail(VOFL_ERR_INVALID, "plan is NULL");
+    if (!u || !out) return fail(VOFL_ERR_INVALID, "u and out must be device pointers");
+    if (u == out) return fail(VOFL_ERR_INVALID, "out must not alias u");
+    if (op != VOFL_OP_S1 && op != VOFL_OP_S2) return fail(VOFL_ERR_INVALID, "op must be VOFL_OP_S1 or VOFL_OP_S2");
+    if (op == VOFL_OP_S2 && p->model == VOFL_MODEL_GENERIC)
+        return fail(VOFL_ERR_INVALID, "VOFL_OP_S2 belongs to the seismic model");
+    if (nfields < 1 || nfields > p->g.max_batch) return fail(VOFL_ERR_INVALID, "nfields must be in [1, max_batch]");
+    if (p->g.ncoef > 1 && nfields > p->g.ncoef)
+        return fail(VOFL_ERR_INVALID, "nfields exceeds the number of coefficient fields");
+    hipStream_t s = (hipStream_t)stream;
+    return p->precision == VOFL_FP32 ? apply_any<float>(p, op, u, out, nfields, s)
+                                     : apply_any<double>(p, op, u, out, nfields, s);
+}
+
+int vofl_step(vofl_plan_t p, void* u, void* v, int nsteps, void* stream) {
+    if (!p) return fail(VOFL_ERR_INVALID, "plan is NULL");
+    if (!u || !v) return fail(VOFL_ERR_INVALID, "u and v must be device pointers");
+    if (u == v) return fail(VOFL_ERR_INVALID, "u and v must be distinct");
+    if (nsteps < 0) return fail(VOFL_ERR_INVALID, "nsteps must be >= 0");
+    hipStream_t s = (hipStream_t)stream;
+    return p->precision == VOFL_FP32 ? step_any<float>(p, u, v, nsteps, s)
+                                     : step_any<double>(p, u, v, nsteps, s);
+}
+
+int vofl_solve(vofl_plan_t p, const void* u0, const void* v0, int nsteps, void* u, void* v, void* stream) {
+    if (!p) return fail(VOFL_ERR_INVALID, "plan is NULL");
+    if (!u0 || !v0 || !u || !v) return fail(VOFL_ERR_INVALID, "null device pointer");
+    hipStream_t s = (hipStream_t)stream;
+    const size_t bytes = (size_t)p->g.batch * p->g.Nreal * p->g.elt;
+    hipError_t e = hipSuccess;
+    if (u0 != u) e = hipMemcpyAsync(u, u0, bytes, hipMemcpyDeviceToDevice, s);
+    if (e == hipSuccess && v0 != v) e = hipMemcpyAsync(v, v0, bytes, hipMemcpyDeviceToDevice, s);
+    if (e != hipSuccess) return hip_fail(e, "initial copy");
+    return vofl_step(p, u, v, nsteps, stream);
+}
+
+int vofl_step_batch(vofl_plan_t* plans, void** u, void** v, const int* nsteps, int count, void* stream) {
+    if (!plans || !u || !v || !nsteps || count < 0) return fail(VOFL_ERR_INVALID, "null argument");
+    hipStream_t s = (hipStream_t)stream;
+    // fork: every plan runs on its own stream after the caller's prior work
+    hipEvent_t start = nullptr;
+    hipError_t e = hipEventCreateWithFlags(&start, hipEventDisableTiming);
+    if (e != hipSuccess) return hip_fail(e, "event");
+    (void)hipEventRecord(start, s);
+    int rc = VOFL_OK;
+    for (int i = 0; i < count && rc == VOFL_OK; ++i) {
+        vofl_plan_s* p = plans[i];
+        if (!p) {
+            rc = fail(VOFL_ERR_INVALID, "plans[%d] is NULL", i);
+            break;
+        }
+        if (!p->own_stream) {
+            e = hipStreamCreateWithFlags(&p->own_stream, hipStreamNonBlocking);
+            if (e == hipSuccess) e = hipEventCreateWithFlags(&p->join_ev, hipEventDisableTiming);
+            if (e != hipSuccess) {
+                rc = hip_fail(e, "stream");
+                break;
+            }
+        }
+        (void)hipStreamWaitEvent(p->own_stream, start, 0);
+        rc = vofl_step(p, u[i], v[i], nsteps[i], p->own_stream);
+        (void)hipEventRecord(p->join_ev, p->own_stream);
+    }
+    for (int i = 0; i < count; ++i)
+        if (plans[i] && plans[i]->join_ev) (void)hipStreamWaitEvent(s, plans[i]->join_ev, 0);
+    (void)hipEventDestroy(start);
+    return rc;
+}
+
+int vofl_sync_status(vofl_plan_t p, void* stream) {
+    if (!p) return fail(VOFL_ERR_INVALID, "plan is NULL");
+    hipError_t e = hipStreamSynchronize((hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e, "stream synchronize");
+    int flag = 0;
+    e = hipMemcpy(&flag, p->flag, sizeof(int), hipMemcpyDeviceToHost);
+    if (e != hipSuccess) return hip_fail(e, "flag read");
+    if (flag) {
+        e = hipMemset(p->flag, 0, sizeof(int));
+        if (e != hipSuccess) return hip_fail(e, "flag reset");
+        return fail(VOFL_ERR_UNSTABLE, "non-finite value during a step (time step above the stability limit?)");
+    }
+    return VOFL_OK;
+}
+
+int vofl_set_timing(vofl_plan_t p, int enable) {
+    if (!p) return fail(VOFL_ERR_INVALID, "plan is NULL");
+    p->timing = enable != 0;
+    if (enable) p->totals.clear();
+    return VOFL_OK;
+}
+
+int vofl_kernel_times(vofl_plan_t p, const char** names, double* ms, long long* launches, int cap) {
+    if (!p) return fail(VOFL_ERR_INVALID, "plan is NULL");
+    p->drain_timing();
+    int k = 0;
+    for (auto& kv : p->totals) {
+        if (k < cap) {
+            if (names) names[k] = p->cls_names[kv.first].c_str();
+            if (ms) ms[k] = kv.second.first;
+            if (launches) launches[k] = kv.second.second;
+        }
+        ++k;
+    }
+    return k;
+}
+
+int vofl_plan_info(vofl_plan_t p, double* out, int cap) {
+    if (!p || !out) return fail(VOFL_ERR_INVALID, "null argument");
+    const double v[5] = {p->model == VOFL_MODEL_GENERIC ? p->sc_host[0].sig1 : p->sc_host[0].sig1 - 1.0,
+                         p->sc_host[0].kappa0, p->sc_host[0].beta0, (double)p->g.Nreal, (double)p->g.bytes};
+    for (int i = 0; i < cap && i < 5; ++i) out[i] = v[i];
+    return VOFL_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,36 @@
+"""Shared helpers of the GPU tests: device transfer and plan construction."""
+
+import numpy as np
+
+TOL_FP64 = 1e-12   # relative L2, FP64 path vs FP64 oracle
+TOL_FP32 = 1e-5    # relative L2, FP32 path (FP64 coefficients/state) vs FP64 oracle
+
+
+def require_gpu():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a HIP device (no CPU fallback exists)"
+    return torch
+
+
+def dev(x, precision):
+    import torch
+    dt = torch.float32 if precision == "fp32" else torch.float64
+    return torch.from_numpy(np.ascontiguousarray(np.asarray(x, dtype=np.float64))).to("cuda", dt)
+
+
+def host(t):
+    return t.detach().double().cpu().numpy()
+
+
+def rel_l2(a, b):
+    a = np.asarray(a, dtype=np.float64).ravel()
+    b = np.asarray(b, dtype=np.float64).ravel()
+    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
+
+
+def tol(precision):
+    return TOL_FP32 if precision == "fp32" else TOL_FP64
+
+
+def say(msg):
+    print(msg, flush=True)
