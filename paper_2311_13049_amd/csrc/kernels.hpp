@@ -109,39 +109,45 @@ constexpr int c2r_width() {
 // ---------------------------------------------------------------------------
 // k_contig: last-axis pencils
 // ---------------------------------------------------------------------------
-template <typename T>
+template <typename T, typename TI>
 struct ContigArgs {
-    const cpx<T>* in;        // input half fields: item b, field f at in + (b*in_slots + in_slot0 + f)*H
-    int in_slots, in_slot0, nin;
+    const cpx<TI>* in;       // input half fields: item b, field f at in + b*in_istride + f*in_fstride
+    long long in_istride, in_fstride;
+    int nin;
     cpx<double>* U;          // spectral state u_hat, item b at U + b*H
     cpx<double>* V;          // spectral state v_hat
-    cpx<T>* out;             // output slots: item b, slot s at out + (b*out_slots + out_slot0 + s)*H
-    int out_slots, out_slot0;
+    cpx<T>* out;             // output slots: item b, slot s at out + b*out_istride + s*H
+    long long out_istride;
     long long H;             // complex elements of one half field
     int npencils;            // pencils of one field
     int n1;                  // pencils per k0 plane (3D: n1, 2D: 1)
     const double* mu2_0;     // mu^2 of axis 0 by bin
     const double* mu2_1;     // axis 1 (3D) or null
     const double* mu2_l;     // last axis
-    const cpx<T>* tw;        // last-axis twiddle table
+    const cpx<TI>* tw_in;    // last-axis twiddles for the input transform (precision TI)
+    const cpx<T>* tw;        // last-axis twiddles for the output transforms
     const SolveScalars* sc;  // per item (sc_stride 1) or shared (0)
     int sc_stride;
     int in_kind, emit_kind, do_prop, M, op;
     double tprop, dt, invN;
 };
 
-template <typename T, int N, int E, int P>
-__global__ __launch_bounds__(P*(N / E)) void k_contig(ContigArgs<T> a) {
+// Input spectra (forward transforms of caller data, and the FP64 staging)
+// are transformed in precision TI; the term spectra in precision T.
+template <typename T, typename TI, int N, int E, int P>
+__global__ __launch_bounds__(P*(N / E)) void k_contig(ContigArgs<T, TI> a) {
     constexpr int TP = N / E;
+    constexpr int FPI = LdsPencil<TI>::footprint(N);
     constexpr int FP = LdsPencil<T>::footprint(N);
-    __shared__ cpx<T> lds_raw[P * FP];
+    __shared__ cpx<TI> lds_raw[P * FPI];  // holds P pencils of TI (>= size of T)
     const int lp = threadIdx.x / TP;
     const int t = threadIdx.x % TP;
     const int p = blockIdx.x * P + lp;
     const int bi = blockIdx.y;
     const bool active = p < a.npencils;
     const int pc = active ? p : 0;
-    const LdsPencil<T> lds{lds_raw + lp * FP};
+    const LdsPencil<TI> ldsi{lds_raw + lp * FPI};
+    const LdsPencil<T> lds{reinterpret_cast<cpx<T>*>(lds_raw) + lp * FP};
     const int k0 = pc / a.n1;
     const int k1 = pc % a.n1;
     const double m2base = a.mu2_0[k0] + (a.mu2_1 ? a.mu2_1[k1] : 0.0);
@@ -150,11 +156,11 @@ __global__ __launch_bounds__(P*(N / E)) void k_contig(ContigArgs<T> a) {
 
     cpx<double> uh[E], vh[E];
     if (a.in_kind == IN_KICK) {
-        cpx<T> d[E];
-        const cpx<T>* src = a.in + ((long long)bi * a.in_slots + a.in_slot0) * a.H + pen;
+        cpx<TI> d[E];
+        const cpx<TI>* src = a.in + (long long)bi * a.in_istride + pen;
 #pragma unroll
         for (int e = 0; e < E; ++e) d[e] = src[t + TP * e];
-        fft_pencil<T, N, E, -1>(d, t, lds, a.tw);
+        fft_pencil<TI, N, E, -1>(d, t, ldsi, a.tw_in);
         const cpx<double>* Us = a.U + (long long)bi * a.H + pen;
         const cpx<double>* Vs = a.V + (long long)bi * a.H + pen;
         const double s = a.dt * a.invN;
@@ -166,11 +172,11 @@ __global__ __launch_bounds__(P*(N / E)) void k_contig(ContigArgs<T> a) {
         }
     } else {
         for (int f = 0; f < a.nin; ++f) {
-            cpx<T> d[E];
-            const cpx<T>* src = a.in + ((long long)bi * a.in_slots + a.in_slot0 + f) * a.H + pen;
+            cpx<TI> d[E];
+            const cpx<TI>* src = a.in + (long long)bi * a.in_istride + (long long)f * a.in_fstride + pen;
 #pragma unroll
             for (int e = 0; e < E; ++e) d[e] = src[t + TP * e];
-            fft_pencil<T, N, E, -1>(d, t, lds, a.tw);
+            fft_pencil<TI, N, E, -1>(d, t, ldsi, a.tw_in);
 #pragma unroll
             for (int e = 0; e < E; ++e) {
                 const cpx<double> z = {double(d[e].x) * a.invN, double(d[e].y) * a.invN};
@@ -223,7 +229,7 @@ __global__ __launch_bounds__(P*(N / E)) void k_contig(ContigArgs<T> a) {
         }
     }
 
-    cpx<T>* dst0 = a.out + ((long long)bi * a.out_slots + a.out_slot0) * a.H + pen;
+    cpx<T>* dst0 = a.out + (long long)bi * a.out_istride + pen;
     if (a.emit_kind == EMIT_GENERIC) {
         // slot M+1: u_hat itself (inverse along the last axis)
         {
@@ -304,8 +310,9 @@ __global__ __launch_bounds__(P*(N / E)) void k_contig(ContigArgs<T> a) {
 // ---------------------------------------------------------------------------
 template <typename T>
 struct MidArgs {
-    cpx<T>* buf;            // item b, slot s at buf + (b*slots + s)*H
-    int slots, slot0, nf;   // fields [slot0, slot0 + nf) of each item
+    cpx<T>* buf;            // item b, field f at buf + b*istride + f*H
+    long long istride;
+    int nf;                 // fields per item
     long long H;
     int n2;                 // columns of a k0 plane (last axis length)
     int tiles_per_plane;    // ceil(n2 / W)
@@ -324,7 +331,7 @@ __global__ __launch_bounds__(W*(N / E)) void k_mid(MidArgs<T> a) {
     const int colc = active ? col : 0;
     const int item = blockIdx.y / a.nf;
     const int f = blockIdx.y % a.nf;
-    cpx<T>* base = a.buf + ((long long)item * a.slots + a.slot0 + f) * a.H +
+    cpx<T>* base = a.buf + (long long)item * a.istride + (long long)f * a.H +
                    (long long)plane * N * a.n2 + colc;
     const LdsColumn<T, W> lds{lds_raw + c};
     cpx<T> v[E];
@@ -340,43 +347,43 @@ __global__ __launch_bounds__(W*(N / E)) void k_mid(MidArgs<T> a) {
 // ---------------------------------------------------------------------------
 // k_r2c0: axis-0 forward transform of real fields -> half spectra
 // ---------------------------------------------------------------------------
-template <typename T>
+template <typename TR>
 struct R2CArgs {
-    const T* in;            // real fields: item b, field f at in + (b*nf + f)*Nreal
-    int nf;
+    const TR* in;           // real fields: item b at in + b*Nreal
     long long Nreal;
-    cpx<T>* out;            // half fields: item b, field f at out + (b*slots + slot0 + f)*H
-    int slots, slot0;
+    cpx<double>* out;       // FP64 half spectra: item b at out + b*H
     long long H;
     int inner;              // columns (product of the other axes)
-    const cpx<T>* tw;       // axis-0 twiddles
+    const cpx<double>* tw;  // axis-0 twiddles (FP64)
 };
 
-template <typename T, int N, int E, int W>
-__global__ __launch_bounds__(W*(N / E)) void k_r2c0(R2CArgs<T> a) {
+// Forward axis-0 transform of caller data, in FP64 whatever the plan
+// precision: the operator amplifies rounding noise of the input spectrum by
+// up to |mu_max|^{2 s}, so the first transform is kept exact to FP64.
+template <typename TR, int N, int E, int W>
+__global__ __launch_bounds__(W*(N / E)) void k_r2c0(R2CArgs<TR> a) {
     constexpr int TP = N / E;
-    __shared__ cpx<T> lds_raw[N * W];
+    __shared__ cpx<double> lds_raw[N * W];
     const int c = threadIdx.x % W;
     const int t = threadIdx.x / W;
     const int col = blockIdx.x * W + c;
     const bool active = col < a.inner;
     const int colc = active ? col : 0;
-    const int item = blockIdx.y / a.nf;
-    const int f = blockIdx.y % a.nf;
-    const T* src = a.in + ((long long)item * a.nf + f) * a.Nreal + colc;
-    const LdsColumn<T, W> lds{lds_raw + c};
-    cpx<T> v[E];
+    const int item = blockIdx.y;
+    const TR* src = a.in + (long long)item * a.Nreal + colc;
+    const LdsColumn<double, W> lds{lds_raw + c};
+    cpx<double> v[E];
 #pragma unroll
-    for (int e = 0; e < E; ++e) v[e] = {src[(long long)(t + TP * e) * a.inner], T(0)};
-    fft_pencil<T, N, E, -1>(v, t, lds, a.tw);
+    for (int e = 0; e < E; ++e) v[e] = {double(src[(long long)(t + TP * e) * a.inner]), 0.0};
+    fft_pencil<double, N, E, -1>(v, t, lds, a.tw);
     if (active) {
-        cpx<T>* dst = a.out + ((long long)item * a.slots + a.slot0 + f) * a.H + colc;
+        cpx<double>* dst = a.out + (long long)item * a.H + colc;
 #pragma unroll
         for (int e = 0; e < E; ++e) {
             const int k = t + TP * e;
             if (k <= N / 2) {
-                cpx<T> z = v[e];
-                if (k == 0 || k == N / 2) z.y = T(0);
+                cpx<double> z = v[e];
+                if (k == 0 || k == N / 2) z.y = 0.0;
                 dst[(long long)k * a.inner] = z;
             }
         }
@@ -388,8 +395,8 @@ __global__ __launch_bounds__(W*(N / E)) void k_r2c0(R2CArgs<T> a) {
 // ---------------------------------------------------------------------------
 template <typename T>
 struct C2RArgs {
-    const cpx<T>* in;       // half slots: item b, slot s at in + (b*slots + s)*H
-    int slots;
+    const cpx<T>* in;       // half slots: item b, slot s at in + b*istride + s*H
+    long long istride;
     long long H;
     int inner;
     const cpx<T>* tw;       // axis-0 twiddles
@@ -402,8 +409,7 @@ struct C2RArgs {
     const SolveScalars* sc;
     int sc_stride;
     // outputs
-    cpx<T>* dv_out;         // kick: half field at dv_out + (b*slots + dv_slot)*H
-    int dv_slot;
+    cpx<T>* dv_out;         // kick: half field of item b at dv_out + b*istride
     T* r0;                  // apply: out; export: u (item b at r0 + b*Nreal)
     T* r1;                  // export: v
     long long Nreal;
@@ -446,7 +452,7 @@ __global__ __launch_bounds__(W*(N / E)) void k_c2r0(C2RArgs<T> a) {
     const int colc = active ? col : 0;
     const int item = blockIdx.y;
     const LdsColumn<T, W> lds{lds_fft + c};
-    const cpx<T>* ibase = a.in + (long long)item * a.slots * a.H;
+    const cpx<T>* ibase = a.in + (long long)item * a.istride;
 
     // stage rows 0..N/2 of one or two half slots into LDS (coalesced)
     auto stage = [&](int s1, int s2) {
@@ -565,7 +571,7 @@ __global__ __launch_bounds__(W*(N / E)) void k_c2r0(C2RArgs<T> a) {
         if (bad && active) a.flag[0] = 1;
         fft_pencil<T, N, E, -1>(z, t, lds, a.tw);
         if (active) {
-            cpx<T>* dst = a.dv_out + ((long long)item * a.slots + a.dv_slot) * a.H + colc;
+            cpx<T>* dst = a.dv_out + (long long)item * a.istride + colc;
 #pragma unroll
             for (int e = 0; e < E; ++e) {
                 const int k = t + TP * e;
@@ -625,7 +631,7 @@ __global__ __launch_bounds__(W*(N / E)) void k_c2r0(C2RArgs<T> a) {
     }
     fft_pencil<T, N, E, -1>(z, t, lds, a.tw);
     if (active) {
-        cpx<T>* dst = a.dv_out + ((long long)item * a.slots + a.dv_slot) * a.H + colc;
+        cpx<T>* dst = a.dv_out + (long long)item * a.istride + colc;
 #pragma unroll
         for (int e = 0; e < E; ++e) {
             const int k = t + TP * e;
@@ -649,7 +655,8 @@ struct Args1D {
     T* v_out;
     int N;
     const double* mu2;      // axis table
-    const cpx<T>* tw;
+    const cpx<T>* tw;       // twiddles in the working precision
+    const cpx<double>* tw64;  // FP64 twiddles for the forward transform of caller data
     const double* delta;    // per point (stride coef_stride per item)
     const T* A;
     const T* B;
@@ -664,16 +671,17 @@ struct Args1D {
 template <typename T, int N, int E>
 __global__ __launch_bounds__(N / E) void k_1d_apply(Args1D<T> a) {
     constexpr int TP = N / E;
-    __shared__ cpx<T> lds_raw[LdsPencil<T>::footprint(N)];
-    const LdsPencil<T> lds{lds_raw};
+    __shared__ cpx<double> lds_raw[LdsPencil<double>::footprint(N)];
+    const LdsPencil<double> lds64{lds_raw};
+    const LdsPencil<T> lds{reinterpret_cast<cpx<T>*>(lds_raw)};
     const int t = threadIdx.x;
     const int item = blockIdx.x;
     const SolveScalars sc = a.sc[item * a.sc_stride];
     const T* u = a.u_in + (long long)item * N;
-    cpx<T> x[E];
+    cpx<double> x[E];  // forward transform of the input in FP64
 #pragma unroll
-    for (int e = 0; e < E; ++e) x[e] = {u[t + TP * e], T(0)};
-    fft_pencil<T, N, E, -1>(x, t, lds, a.tw);
+    for (int e = 0; e < E; ++e) x[e] = {double(u[t + TP * e]), 0.0};
+    fft_pencil<double, N, E, -1>(x, t, lds64, a.tw64);
     const double sig = (a.op == 2) ? sc.sig2 : sc.sig1;
     cpx<double> r[E];
     double L[E], dl[E], acc[E], dp[E];
@@ -732,27 +740,28 @@ __device__ __forceinline__ void mode_symbols(double m2, double sig1, double sig2
 template <typename T, int N, int E>
 __global__ __launch_bounds__(N / E) void k_1d_step(Args1D<T> a) {
     constexpr int TP = N / E;
-    __shared__ cpx<T> lds_raw[LdsPencil<T>::footprint(N)];
-    const LdsPencil<T> lds{lds_raw};
+    __shared__ cpx<double> lds_raw[LdsPencil<double>::footprint(N)];
+    const LdsPencil<double> lds64{lds_raw};
+    const LdsPencil<T> lds{reinterpret_cast<cpx<T>*>(lds_raw)};
     const int t = threadIdx.x;
     const int item = blockIdx.x;
     const SolveScalars sc = a.sc[item * a.sc_stride];
     const long long co = (long long)item * a.coef_stride;
     cpx<double> uh[E], vh[E];
     {
-        cpx<T> x[E];
+        cpx<double> x[E];  // forward transforms of the caller's (u, v) in FP64
         const T* u = a.u_in + (long long)item * N;
 #pragma unroll
-        for (int e = 0; e < E; ++e) x[e] = {u[t + TP * e], T(0)};
-        fft_pencil<T, N, E, -1>(x, t, lds, a.tw);
+        for (int e = 0; e < E; ++e) x[e] = {double(u[t + TP * e]), 0.0};
+        fft_pencil<double, N, E, -1>(x, t, lds64, a.tw64);
 #pragma unroll
-        for (int e = 0; e < E; ++e) uh[e] = {double(x[e].x) * a.invN, double(x[e].y) * a.invN};
+        for (int e = 0; e < E; ++e) uh[e] = {x[e].x * a.invN, x[e].y * a.invN};
         const T* v = a.v_in + (long long)item * N;
 #pragma unroll
-        for (int e = 0; e < E; ++e) x[e] = {v[t + TP * e], T(0)};
-        fft_pencil<T, N, E, -1>(x, t, lds, a.tw);
+        for (int e = 0; e < E; ++e) x[e] = {double(v[t + TP * e]), 0.0};
+        fft_pencil<double, N, E, -1>(x, t, lds64, a.tw64);
 #pragma unroll
-        for (int e = 0; e < E; ++e) vh[e] = {double(x[e].x) * a.invN, double(x[e].y) * a.invN};
+        for (int e = 0; e < E; ++e) vh[e] = {x[e].x * a.invN, x[e].y * a.invN};
     }
     auto propagate = [&](double tp) {
 #pragma unroll

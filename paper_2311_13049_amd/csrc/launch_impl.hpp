@@ -41,6 +41,16 @@ int Launch<T>::tile_w(int N) {
 }
 
 template <typename T>
+int Launch<T>::r2c0_w(int N) {
+    switch (N) {
+#define C_(n) case n: return tile_width<double, n>();
+        VOFL_MULTI_SIZES(C_)
+#undef C_
+        default: return 0;
+    }
+}
+
+template <typename T>
 int Launch<T>::c2r_w(int N) {
     switch (N) {
 #define C_(n) case n: return c2r_width<T, n>();
@@ -51,13 +61,14 @@ int Launch<T>::c2r_w(int N) {
 }
 
 template <typename T>
-hipError_t Launch<T>::contig(int N, const ContigArgs<T>& a, int items, hipStream_t s) {
+template <typename TI>
+hipError_t Launch<T>::contig(int N, const ContigArgs<T, TI>& a, int items, hipStream_t s) {
     switch (N) {
 #define C_(n)                                                                           \
     case n: {                                                                           \
         constexpr int E = e_contig(n), P = p_contig(n);                                 \
         dim3 grid((a.npencils + P - 1) / P, items);                                     \
-        k_contig<T, n, E, P><<<grid, dim3(P * (n / E)), 0, s>>>(a);                     \
+        k_contig<T, TI, n, E, P><<<grid, dim3(P * (n / E)), 0, s>>>(a);                 \
         return hipGetLastError();                                                       \
     }
         VOFL_MULTI_SIZES(C_)
@@ -89,8 +100,8 @@ hipError_t Launch<T>::r2c0(int N, const R2CArgs<T>& a, int items, hipStream_t s)
     switch (N) {
 #define C_(n)                                                                           \
     case n: {                                                                           \
-        constexpr int E = e_r2c0(n), W = tile_width<T, n>();                            \
-        dim3 grid((a.inner + W - 1) / W, items * a.nf);                                 \
+        constexpr int E = e_r2c0(n), W = tile_width<double, n>();                       \
+        dim3 grid((a.inner + W - 1) / W, items);                                        \
         k_r2c0<T, n, E, W><<<grid, dim3(W * (n / E)), 0, s>>>(a);                       \
         return hipGetLastError();                                                       \
     }

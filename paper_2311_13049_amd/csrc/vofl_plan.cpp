@@ -57,6 +57,7 @@ struct Geometry {
     int batch = 1, max_batch = 1, ncoef = 1;
     int nterm = 0;         // term slots of one step
     int step_slots = 0, apply_slots = 0;
+    int stage_fields = 0;  // FP64 half fields of the state/staging block
     size_t elt = 0;        // bytes of one working-precision real
     size_t bytes = 0;      // total device bytes
 };
@@ -128,8 +129,8 @@ int derive(const vofl_desc* d, Geometry& g) {
     g.elt = is_fp32(d) ? 4 : 8;
     const size_t celt = 2 * g.elt;
     size_t bytes = 0;
-    // per-axis tables: twiddles (working precision) and mu^2 (FP64)
-    for (int i = 0; i < d->ndim; ++i) bytes += g.n[i] * (celt + 8);
+    // per-axis tables: twiddles (working precision and FP64) and mu^2 (FP64)
+    for (int i = 0; i < d->ndim; ++i) bytes += g.n[i] * (celt + 16 + 8);
     // per-point coefficients: delta (FP64), A and B (working precision), scalars
     bytes += (size_t)ncv * (8 + 2 * g.elt) + (size_t)g.ncoef * sizeof(SolveScalars) + 256;
     if (d->ndim >= 2) {
@@ -139,14 +140,15 @@ int derive(const vofl_desc* d, Geometry& g) {
         g.H = (long long)g.n0h * g.inner;
         g.npencils = (int)(g.H / g.nlast);
         g.nterm = (d->model == VOFL_MODEL_SEISMIC) ? 2 * (d->M + 1) : d->M + 2;
-        g.step_slots = g.nterm + 3;
-        g.apply_slots = d->M + 2;
+        g.step_slots = g.nterm + 3;   // terms, dv, export pair
+        g.apply_slots = d->M + 1;     // terms
         const long long slots =
             std::max((long long)g.batch * g.step_slots, (long long)g.max_batch * g.apply_slots);
         if ((long long)g.batch * g.step_slots > 65535 || (long long)g.max_batch * g.apply_slots > 65535)
             return fail(VOFL_ERR_INVALID, "batch x slots exceeds the launch grid limit");
         bytes += (size_t)slots * g.H * celt;                  // work slots
-        bytes += (size_t)2 * g.batch * g.H * 16;              // FP64 spectral state
+        g.stage_fields = std::max(2 * g.batch, g.max_batch);
+        bytes += (size_t)g.stage_fields * g.H * 16;           // FP64 state / forward staging
     }
     g.bytes = bytes;
     if (d->hbm_budget && bytes > d->hbm_budget)
@@ -179,7 +181,8 @@ struct vofl_plan_s {
     std::vector<SolveScalars> sc_host;
     // device memory
     double* mu2[3] = {nullptr, nullptr, nullptr};
-    void* tw[3] = {nullptr, nullptr, nullptr};
+    void* tw[3] = {nullptr, nullptr, nullptr};      // working precision
+    cpx<double>* tw64[3] = {nullptr, nullptr, nullptr};
     double* delta = nullptr;
     void* A = nullptr;
     void* B = nullptr;
@@ -283,10 +286,17 @@ int upload_tables(vofl_plan_s* p, const std::vector<double>& delta, const std::v
             const double mu = 2.0 * M_PI * (double)k / L;
             mu2[j] = mu * mu;
         }
+        std::vector<cpx<double>> tw64(n);
+        for (int j = 0; j < n; ++j) {
+            const double ang = 2.0 * M_PI * (double)j / (double)n;
+            tw64[j] = {std::cos(ang), -std::sin(ang)};
+        }
         int rc;
         if ((rc = dalloc(p, (cpx<T>**)&p->tw[ax], n * sizeof(cpx<T>)))) return rc;
+        if ((rc = dalloc(p, &p->tw64[ax], n * sizeof(cpx<double>)))) return rc;
         if ((rc = dalloc(p, &p->mu2[ax], n * sizeof(double)))) return rc;
         hipError_t e = hipMemcpy(p->tw[ax], tw.data(), n * sizeof(cpx<T>), hipMemcpyHostToDevice);
+        if (e == hipSuccess) e = hipMemcpy(p->tw64[ax], tw64.data(), n * sizeof(cpx<double>), hipMemcpyHostToDevice);
         if (e == hipSuccess) e = hipMemcpy(p->mu2[ax], mu2.data(), n * sizeof(double), hipMemcpyHostToDevice);
         if (e != hipSuccess) return hip_fail(e, "table upload");
     }
@@ -312,8 +322,10 @@ int upload_tables(vofl_plan_s* p, const std::vector<double>& delta, const std::v
     if (g.ndim >= 2) {
         const long long slots = std::max((long long)g.batch * g.step_slots, (long long)g.max_batch * g.apply_slots);
         if ((rc = dalloc(p, (cpx<T>**)&p->work, (size_t)slots * g.H * sizeof(cpx<T>)))) return rc;
-        if ((rc = dalloc(p, (cpx<double>**)&p->U, (size_t)g.batch * g.H * sizeof(cpx<double>)))) return rc;
-        if ((rc = dalloc(p, (cpx<double>**)&p->V, (size_t)g.batch * g.H * sizeof(cpx<double>)))) return rc;
+        // one block: u_hat of every solve, then v_hat of every solve; also the
+        // FP64 staging of forward transforms (apply fields use it from the start)
+        if ((rc = dalloc(p, (cpx<double>**)&p->U, (size_t)g.stage_fields * g.H * sizeof(cpx<double>)))) return rc;
+        p->V = (cpx<double>*)p->U + (size_t)g.batch * g.H;
     }
     return VOFL_OK;
 }
@@ -322,10 +334,10 @@ int upload_tables(vofl_plan_s* p, const std::vector<double>& delta, const std::v
 // launch sequences
 // ---------------------------------------------------------------------------
 
-template <typename T>
-ContigArgs<T> contig_base(vofl_plan_s* p) {
+template <typename T, typename TI>
+ContigArgs<T, TI> contig_base(vofl_plan_s* p) {
     const Geometry& g = p->g;
-    ContigArgs<T> a{};
+    ContigArgs<T, TI> a{};
     a.H = g.H;
     a.npencils = g.npencils;
     a.n1 = (g.ndim == 3) ? g.n[1] : 1;
@@ -343,21 +355,38 @@ ContigArgs<T> contig_base(vofl_plan_s* p) {
     return a;
 }
 
+// 3D middle-axis transform of nf fields per item (item stride istride)
 template <typename T>
-hipError_t mid(vofl_plan_s* p, int dir, int slots, int slot0, int nf, int items, hipStream_t s) {
+hipError_t mid(vofl_plan_s* p, int dir, cpx<T>* buf, long long istride, int nf, int items,
+               const cpx<T>* tw, hipStream_t s) {
     const Geometry& g = p->g;
     if (g.ndim != 3) return hipSuccess;
     MidArgs<T> m{};
-    m.buf = (cpx<T>*)p->work;
-    m.slots = slots;
-    m.slot0 = slot0;
+    m.buf = buf;
+    m.istride = istride;
     m.nf = nf;
     m.H = g.H;
     m.n2 = g.n[2];
     const int W = Launch<T>::tile_w(g.n[1]);
     m.tiles_per_plane = (g.n[2] + W - 1) / W;
-    m.tw = (const cpx<T>*)p->tw[1];
+    m.tw = tw;
     return p->timed("mid", s, [&] { return Launch<T>::mid(g.n[1], dir, m, g.n0h, items, s); });
+}
+
+// forward transform of real fields (items of Nreal values) into the FP64
+// staging block at stage + item*H, including the 3D middle axis
+template <typename T>
+hipError_t forward_to_stage(vofl_plan_s* p, const T* in, cpx<double>* stage, int items, hipStream_t s) {
+    const Geometry& g = p->g;
+    R2CArgs<T> r{};
+    r.in = in;
+    r.Nreal = g.Nreal;
+    r.out = stage;
+    r.H = g.H;
+    r.inner = g.inner;
+    r.tw = p->tw64[0];
+    hipError_t e = p->timed("r2c0", s, [&] { return Launch<T>::r2c0(g.n[0], r, items, s); });
+    return e;
 }
 
 template <typename T>
@@ -383,40 +412,31 @@ C2RArgs<T> c2r_base(vofl_plan_s* p) {
 template <typename T>
 int apply_multi(vofl_plan_s* p, int op, const T* u, T* out, int nf, hipStream_t s) {
     const Geometry& g = p->g;
-    const int A = g.apply_slots, M = p->M;
+    const long long AS = (long long)g.apply_slots * g.H;  // item stride of the term slots
     cpx<T>* W = (cpx<T>*)p->work;
-    hipError_t e;
-    R2CArgs<T> r{};
-    r.in = u;
-    r.nf = 1;
-    r.Nreal = g.Nreal;
-    r.out = W;
-    r.slots = A;
-    r.slot0 = M + 1;
-    r.H = g.H;
-    r.inner = g.inner;
-    r.tw = (const cpx<T>*)p->tw[0];
-    e = p->timed("r2c0", s, [&] { return Launch<T>::r2c0(g.n[0], r, nf, s); });
+    cpx<double>* stage = (cpx<double>*)p->U;
+    hipError_t e = forward_to_stage<T>(p, u, stage, nf, s);
     if (e != hipSuccess) return hip_fail(e, "r2c0 launch");
-    if ((e = mid<T>(p, -1, A, M + 1, 1, nf, s)) != hipSuccess) return hip_fail(e, "mid launch");
-    ContigArgs<T> a = contig_base<T>(p);
-    a.in = W;
-    a.in_slots = A;
-    a.in_slot0 = M + 1;
+    if ((e = mid<double>(p, -1, stage, g.H, 1, nf, p->tw64[1 % g.ndim], s)) != hipSuccess)
+        return hip_fail(e, "mid launch");
+    ContigArgs<T, double> a = contig_base<T, double>(p);
+    a.in = stage;
+    a.in_istride = g.H;
     a.nin = 1;
+    a.tw_in = p->tw64[g.ndim - 1];
     a.out = W;
-    a.out_slots = A;
-    a.out_slot0 = 0;
+    a.out_istride = AS;
     a.in_kind = IN_APPLY;
     a.emit_kind = EMIT_APPLY;
     a.do_prop = 0;
     a.op = op;
     e = p->timed("contig_apply", s, [&] { return Launch<T>::contig(g.nlast, a, nf, s); });
     if (e != hipSuccess) return hip_fail(e, "contig launch");
-    if ((e = mid<T>(p, +1, A, 0, M + 1, nf, s)) != hipSuccess) return hip_fail(e, "mid launch");
+    if ((e = mid<T>(p, +1, W, AS, p->M + 1, nf, (const cpx<T>*)p->tw[1 % g.ndim], s)) != hipSuccess)
+        return hip_fail(e, "mid launch");
     C2RArgs<T> c = c2r_base<T>(p);
     c.in = W;
-    c.slots = A;
+    c.istride = AS;
     c.mode = C2R_APPLY;
     c.r0 = out;
     e = p->timed("c2r0_apply", s, [&] { return Launch<T>::c2r0(g.n[0], c, nf, s); });
@@ -428,73 +448,74 @@ template <typename T>
 int step_multi(vofl_plan_s* p, T* u, T* v, int nsteps, hipStream_t s) {
     if (nsteps == 0) return VOFL_OK;
     const Geometry& g = p->g;
-    const int S = g.step_slots, nterm = g.nterm;
+    const long long SS = (long long)g.step_slots * g.H;  // item stride of the step slots
+    const int nterm = g.nterm;
     const int dv = nterm, h0 = nterm + 1;
     const int items = g.batch;
     const bool generic = p->model == VOFL_MODEL_GENERIC;
     const int emit_terms = generic ? EMIT_GENERIC : EMIT_STEP;
     cpx<T>* W = (cpx<T>*)p->work;
+    const cpx<T>* twm = (const cpx<T>*)p->tw[1 % g.ndim];
+    cpx<double>* U = (cpx<double>*)p->U;
+    cpx<double>* V = (cpx<double>*)p->V;
     hipError_t e;
 
-    R2CArgs<T> r{};
-    r.nf = 1;
-    r.Nreal = g.Nreal;
-    r.out = W;
-    r.slots = S;
-    r.H = g.H;
-    r.inner = g.inner;
-    r.tw = (const cpx<T>*)p->tw[0];
-    r.in = u;
-    r.slot0 = h0;
-    e = p->timed("r2c0", s, [&] { return Launch<T>::r2c0(g.n[0], r, items, s); });
-    if (e != hipSuccess) return hip_fail(e, "r2c0 launch");
-    r.in = v;
-    r.slot0 = h0 + 1;
-    e = p->timed("r2c0", s, [&] { return Launch<T>::r2c0(g.n[0], r, items, s); });
-    if (e != hipSuccess) return hip_fail(e, "r2c0 launch");
-    if ((e = mid<T>(p, -1, S, h0, 2, items, s)) != hipSuccess) return hip_fail(e, "mid launch");
-
-    ContigArgs<T> a = contig_base<T>(p);
-    a.in = W;
-    a.in_slots = S;
-    a.in_slot0 = h0;
-    a.nin = 2;
-    a.out = W;
-    a.out_slots = S;
-    a.out_slot0 = 0;
-    a.in_kind = IN_INIT;
-    a.emit_kind = emit_terms;
-    a.do_prop = 1;
-    a.tprop = 0.5 * p->dt;
-    e = p->timed("contig_init", s, [&] { return Launch<T>::contig(g.nlast, a, items, s); });
-    if (e != hipSuccess) return hip_fail(e, "contig launch");
+    // forward transforms of (u, v) in FP64 into the state block, then the
+    // first half step of the exact part and the first terms
+    if ((e = forward_to_stage<T>(p, u, U, items, s)) != hipSuccess) return hip_fail(e, "r2c0 launch");
+    if ((e = forward_to_stage<T>(p, v, V, items, s)) != hipSuccess) return hip_fail(e, "r2c0 launch");
+    if ((e = mid<double>(p, -1, U, g.H, 1, 2 * items, p->tw64[1 % g.ndim], s)) != hipSuccess)
+        return hip_fail(e, "mid launch");
+    {
+        ContigArgs<T, double> a = contig_base<T, double>(p);
+        a.in = U;
+        a.in_istride = g.H;
+        a.in_fstride = (long long)items * g.H;
+        a.nin = 2;
+        a.tw_in = p->tw64[g.ndim - 1];
+        a.out = W;
+        a.out_istride = SS;
+        a.in_kind = IN_INIT;
+        a.emit_kind = emit_terms;
+        a.do_prop = 1;
+        a.tprop = 0.5 * p->dt;
+        e = p->timed("contig_init", s, [&] { return Launch<T>::contig(g.nlast, a, items, s); });
+        if (e != hipSuccess) return hip_fail(e, "contig launch");
+    }
 
     C2RArgs<T> c = c2r_base<T>(p);
     c.in = W;
-    c.slots = S;
+    c.istride = SS;
     c.mode = generic ? C2R_KICK_GENERIC : C2R_KICK;
-    c.dv_out = W;
-    c.dv_slot = dv;
+    c.dv_out = W + (long long)dv * g.H;
+
+    ContigArgs<T, T> a = contig_base<T, T>(p);
+    a.in = W + (long long)dv * g.H;
+    a.in_istride = SS;
+    a.nin = 1;
+    a.tw_in = (const cpx<T>*)p->tw[g.ndim - 1];
+    a.out_istride = SS;
+    a.in_kind = IN_KICK;
+    a.do_prop = 1;
 
     for (int st = 0; st < nsteps; ++st) {
         const bool last = (st + 1 == nsteps);
-        if ((e = mid<T>(p, +1, S, 0, nterm, items, s)) != hipSuccess) return hip_fail(e, "mid launch");
+        if ((e = mid<T>(p, +1, W, SS, nterm, items, twm, s)) != hipSuccess) return hip_fail(e, "mid launch");
         e = p->timed("c2r0_kick", s, [&] { return Launch<T>::c2r0(g.n[0], c, items, s); });
         if (e != hipSuccess) return hip_fail(e, "c2r0 launch");
-        if ((e = mid<T>(p, -1, S, dv, 1, items, s)) != hipSuccess) return hip_fail(e, "mid launch");
-        a.in_slot0 = dv;
-        a.nin = 1;
-        a.in_kind = IN_KICK;
+        if ((e = mid<T>(p, -1, W + (long long)dv * g.H, SS, 1, items, twm, s)) != hipSuccess)
+            return hip_fail(e, "mid launch");
         a.tprop = last ? 0.5 * p->dt : p->dt;
         a.emit_kind = last ? EMIT_EXPORT : emit_terms;
-        a.out_slot0 = last ? h0 : 0;
+        a.out = W + (last ? (long long)h0 * g.H : 0);
         e = p->timed("contig_kick", s, [&] { return Launch<T>::contig(g.nlast, a, items, s); });
         if (e != hipSuccess) return hip_fail(e, "contig launch");
     }
-    if ((e = mid<T>(p, +1, S, h0, 2, items, s)) != hipSuccess) return hip_fail(e, "mid launch");
+    if ((e = mid<T>(p, +1, W + (long long)h0 * g.H, SS, 2, items, twm, s)) != hipSuccess)
+        return hip_fail(e, "mid launch");
     C2RArgs<T> x = c2r_base<T>(p);
     x.in = W + (long long)h0 * g.H;
-    x.slots = S;
+    x.istride = SS;
     x.mode = C2R_EXPORT;
     x.r0 = u;
     x.r1 = v;
@@ -510,6 +531,7 @@ Args1D<T> args_1d(vofl_plan_s* p) {
     a.N = g.n[0];
     a.mu2 = p->mu2[0];
     a.tw = (const cpx<T>*)p->tw[0];
+    a.tw64 = p->tw64[0];
     a.delta = p->delta;
     a.A = (const T*)p->A;
     a.B = (const T*)p->B;

@@ -18,6 +18,13 @@ def dev(x, precision):
     return torch.from_numpy(np.ascontiguousarray(np.asarray(x, dtype=np.float64))).to("cuda", dt)
 
 
+def as_seen(x, precision):
+    """The values a plan of this precision receives: x rounded to FP32 for
+    FP32 plans (the oracle is run on exactly these inputs)."""
+    x = np.asarray(x, dtype=np.float64)
+    return x.astype(np.float32).astype(np.float64) if precision == "fp32" else x
+
+
 def host(t):
     return t.detach().double().cpu().numpy()
 
