@@ -1,0 +1,183 @@
+"""Benchmark: TSFP2 steps of the viscoacoustic model (1.1) on a 256^3 grid,
+M = 16, FP32 transforms (FP64 expansion coefficients, multipliers,
+propagator and spectral state), one MI355X.
+
+python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu]
+
+One step is the whole hot path: the exact damped-oscillator sub-steps and
+the kick, which applies both variable-order operators (2.13) (L1 to u and L2
+to v, 2(M+1) inverse transforms) and transforms the kick back. "applies/s"
+counts those two operator applies per step. Prints one JSON line.
+"""
+
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, vendor figure
+WORKLOAD = ("3D periodic [-16,16)^3, 256^3, M=16, two-layer Q (20 above / 100 below, tanh width 1) "
+            "x (1 +- 5% seeded noise), Gaussian pulse u0, v0 = 0, c0 = omega0 = 1, dt = 1e-3")
+
+
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_2311_13049_amd", "csrc")
+    for name in sorted(os.listdir(csrc)):
+        if name.endswith((".hpp", ".hip", ".cpp")):
+            with open(os.path.join(csrc, name), "rb") as f:
+                h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def algorithmic_bytes(cls: str, n: int, M: int, elt: int) -> float:
+    """Bytes one launch of a kernel class must move at least (read + write once).
+
+    N real points, H = (n/2+1) n^2 complex half-spectrum elements, complex of
+    2*elt bytes; state FP64 complex (16 B); delta FP64, A and B elt bytes.
+    """
+    N = n ** 3
+    H = (n // 2 + 1) * n * n
+    c = 2 * elt
+    nterm = 2 * (M + 1)
+    table = {
+        # kick axis-0 pass: read 2(M+1) term slots + delta, A, B; write dv half
+        "c2r0_kick": nterm * H * c + N * (8 + 2 * elt) + H * c,
+        # middle-axis pass over the 2(M+1) term slots (in place)
+        "mid_terms": 2 * nterm * H * c,
+        "mid_dv": 2 * H * c,
+        # last-axis pass: read dv half + state (u_hat, v_hat), write state + 2(M+1) slots
+        "contig_kick": H * c + 4 * H * 16 + nterm * H * c,
+    }
+    return float(table.get(cls, 0.0))
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--n", type=int, default=256)
+    ap.add_argument("--M", type=int, default=16)
+    ap.add_argument("--precision", default="fp32")
+    ap.add_argument("--no-cpu", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print("bench.py runs on one GPU only: the workload is one grid per device, and this "
+              "build has no multi-GPU path (pass --gpus 1).", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    from paper_2311_13049_amd import vofl as V
+    from workloads import c3_inputs
+
+    assert torch.cuda.is_available(), "bench needs a GPU"
+    dev = torch.device("cuda:0")
+    n, M = args.n, args.M
+    c = c3_inputs(n=n)
+    prec = args.precision
+    elt = 4 if prec == "fp32" else 8
+    tdt = torch.float32 if prec == "fp32" else torch.float64
+    plan = V.Plan(c["shape"], c["lo"], c["hi"], Q=c["Q"], M=M, dt=c["dt"], precision=prec,
+                  c0=c["c0"], omega0=c["omega0"], max_batch=2)
+    u = torch.from_numpy(c["u0"]).to(dev, tdt)
+    v = torch.from_numpy(c["v0"]).to(dev, tdt)
+
+    # warmup (untimed)
+    plan.step(u, v, args.warmup)
+    torch.cuda.synchronize()
+
+    # timed: exactly K steps in one call, with per-kernel-class HIP events
+    plan.set_timing(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    plan.step(u, v, args.steps)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    ktimes = plan.kernel_times()
+    plan.set_timing(False)
+    status = plan.sync_status()
+    ms_per_step = (t1 - t0) * 1e3 / args.steps
+    applies_per_s = 2.0 * args.steps / (t1 - t0)
+    N = n ** 3
+
+    # dominant kernel class (largest share of device time)
+    dom = max(ktimes.items(), key=lambda kv: kv[1][0])
+    dom_name, (dom_ms, dom_launches) = dom
+    avg_s = dom_ms / dom_launches / 1e3
+    alg = algorithmic_bytes(dom_name, n, M, elt)
+    achieved = alg / avg_s / 1e9 if alg > 0 else None
+    traffic = None
+    tfile = os.path.join(ROOT, "profiles", f"traffic_{dom_name}_256cube_M16_{prec}.json")
+    if os.path.exists(tfile):
+        with open(tfile) as f:
+            tr = json.load(f)
+        if tr.get("source_hash") == kernel_source_hash():
+            traffic = tr.get("bytes_per_launch")
+
+    # apply-only throughput (b = 2 fields, the L1/L2 pair size), same plan
+    ub = torch.stack([u, v]).contiguous()
+    ob = torch.empty_like(ub)
+    for _ in range(3):
+        plan.apply(V.VOFL_OP_S1, ub, ob)
+    torch.cuda.synchronize()
+    reps = 20
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        plan.apply(V.VOFL_OP_S1, ub, ob)
+    torch.cuda.synchronize()
+    apply_s = (time.perf_counter() - t0) / reps
+    apply_rate = 2.0 / apply_s
+
+    cpu = None
+    if not args.no_cpu:
+        import oracle as O
+        gamma = O.gamma_from_Q(c["Q"])
+        x = c["u0"]
+        t0 = time.perf_counter()
+        O.mterm_apply(x, 1.0 + gamma, c["lo"], c["hi"], M)
+        cpu_s = time.perf_counter() - t0
+        cpu = {"value": 1.0 / cpu_s, "unit": "applies/s", "cores": 1, "kind": "oracle",
+               "sample": f"one oracle apply (2.13) of L1 on the {n}^3 M={M} field, FP64 numpy "
+                         f"(pocketfft, single thread): {cpu_s:.1f} s"}
+
+    out = {
+        "metric": "variable-order applies/s at 256^3, M=16 (two operator applies per TSFP2 step)",
+        "value": applies_per_s,
+        "unit": "applies/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32" if prec == "fp32" else "f64",
+        "data": "synthetic",
+        "config": {"workload": WORKLOAD if n == 256 else WORKLOAD.replace("256^3", f"{n}^3"),
+                   "grid": [n, n, n], "M": M, "precision": prec, "solver": "TSFP2 (3.13)"},
+        "gpts_M_per_s": N * M * applies_per_s / 1e9,
+        "apply_only_b2": {"applies_per_s": apply_rate, "gpts_M_per_s": N * M * apply_rate / 1e9},
+        "roofline": {"bound": "hbm", "kernel": dom_name, "achieved": achieved, "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": (achieved / HBM_PEAK_GBS) if achieved else None,
+                     "traffic": traffic, "alg_bytes_per_launch": alg,
+                     "avg_launch_ms": avg_s * 1e3},
+        "kernel_ms_per_step": {k: ms / args.steps for k, (ms, _) in ktimes.items()},
+        "status": status,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

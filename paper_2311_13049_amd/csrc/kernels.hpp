@@ -97,11 +97,13 @@ constexpr int tile_width() {
     constexpr int col = (N + 2) * int(sizeof(cpx<T>));
     return (16 * col <= 67584) ? 16 : (8 * col <= 67584) ? 8 : 4;
 }
-// Tile width of k_c2r0, which also keeps 8 elements per thread within 512
-// threads per workgroup (register budget of the fused kick).
+// Tile width of k_c2r0: 16 columns unless the FFT buffer (N x W complex)
+// would exceed about 66 KB of LDS, and at most 512 threads at 8 elements
+// per thread.
 template <typename T, int N>
 constexpr int c2r_width() {
-    constexpr int w = tile_width<T, N>();
+    constexpr int col = N * int(sizeof(cpx<T>));
+    constexpr int w = (16 * col <= 67584) ? 16 : (8 * col <= 67584) ? 8 : 4;
     constexpr int lim = (4096 / N) < 4 ? 4 : (4096 / N);
     return w < lim ? w : lim;
 }
@@ -434,49 +436,146 @@ __device__ __forceinline__ cpx<T> hermitian_pair(const cpx<T>* h1, const cpx<T>*
     return {p.x + q.y, q.x - p.y};
 }
 
-template <typename T, int N, int E, int W>
+// Transforms of one k_c2r0 launch: transform i reads the slot pair
+// (2i, 2i+1); the second slot is absent (-1) past the last slot.
+__device__ __forceinline__ int c2r_transforms(int mode, int M) {
+    switch (mode) {
+        case C2R_EXPORT: return 1;
+        case C2R_APPLY: return (M + 2) / 2;         // slots 0..M
+        case C2R_KICK: return M + 1;                // slots 0..2M+1
+        default: return (M + 3) / 2;                // generic: slots 0..M+1
+    }
+}
+__device__ __forceinline__ int c2r_nslots(int mode, int M) {
+    switch (mode) {
+        case C2R_EXPORT: return 2;
+        case C2R_APPLY: return M + 1;
+        case C2R_KICK: return 2 * M + 2;
+        default: return M + 2;
+    }
+}
+
+template <typename T, int N, int E, int W, int MODE>
 __global__ __launch_bounds__(W*(N / E)) void k_c2r0(C2RArgs<T> a) {
+    static_assert(MODE >= 0 && MODE <= 3, "mode");
     constexpr int TP = N / E;
-    constexpr int NT = W * TP;
-    constexpr int HR = N / 2 + 1;  // stored rows
-    // staging (two half columns) and the FFT exchange share one buffer:
-    // a barrier separates the reads of the staged rows from the transform
-    __shared__ cpx<T> lds_fft[2 * HR * W];
-    cpx<T>* h1 = lds_fft;
-    cpx<T>* h2 = lds_fft + HR * W;
+    __shared__ cpx<T> lds_fft[N * W];
     const int c = threadIdx.x % W;
     const int t = threadIdx.x / W;
-    const int col0 = blockIdx.x * W;
-    const int col = col0 + c;
+    const int col = blockIdx.x * W + c;
     const bool active = col < a.inner;
     const int colc = active ? col : 0;
     const int item = blockIdx.y;
     const LdsColumn<T, W> lds{lds_fft + c};
-    const cpx<T>* ibase = a.in + (long long)item * a.istride;
+    const cpx<T>* ibase = a.in + (long long)item * a.istride + colc;
+    const int nT = c2r_transforms(MODE, a.M);
+    const int nS = c2r_nslots(MODE, a.M);
 
-    // stage rows 0..N/2 of one or two half slots into LDS (coalesced)
-    auto stage = [&](int s1, int s2) {
-        for (int i = threadIdx.x; i < HR * W; i += NT) {
-            const int row = i / W, cc = i % W;
-            const int cg = col0 + cc;
-            const bool ok = cg < a.inner;
-            const long long off = (long long)row * a.inner + (ok ? cg : 0);
-            h1[i] = ibase[(long long)s1 * a.H + off];
-            if (s2 >= 0) h2[i] = ibase[(long long)s2 * a.H + off];
+    // Each thread loads, for its rows k = t + TP*e, the stored row
+    // min(k, N-k) of both slots of a pair directly into registers (the
+    // mirror rows of two threads coincide and come from cache the second
+    // time); the next pair is loaded while the current one is transformed.
+    cpx<T> p1[E], p2[E];
+    auto load_pair = [&](int tr) __attribute__((always_inline)) {
+        const int s1 = 2 * tr, s2 = 2 * tr + 1;
+        const bool two = s2 < nS;
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+            const int k = t + TP * e;
+            const int r = (k <= N / 2) ? k : N - k;
+            const long long off = (long long)r * a.inner;
+            p1[e] = ibase[(long long)s1 * a.H + off];
+            p2[e] = two ? ibase[(long long)s2 * a.H + off] : cpx<T>{T(0), T(0)};
         }
-        __syncthreads();
+    };
+    // Y = a + i b with a, b the Hermitian extensions along axis 0
+    auto build = [&](cpx<T> (&y)[E]) __attribute__((always_inline)) {
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+            const int k = t + TP * e;
+            cpx<T> pa = p1[e], pb = p2[e];
+            if (k <= N / 2) {
+                if (k == 0 || k == N / 2) {
+                    pa.y = T(0);
+                    pb.y = T(0);
+                }
+                y[e] = {pa.x - pb.y, pa.y + pb.x};
+            } else {
+                y[e] = {pa.x + pb.y, pb.x - pa.y};
+            }
+        }
     };
 
     // delta at this thread's points (re-read from cache where needed)
     const double* dptr = a.delta + (long long)item * a.coef_stride + colc;
+    const SolveScalars sc = a.sc[item * a.sc_stride];
 
-    if (a.mode == C2R_EXPORT) {
-        stage(0, 1);
-        cpx<T> y[E];
+    // per-mode accumulators:
+    //  apply:   acc = sum_m delta^m t_m (a1 = delta^m)
+    //  kick:    acc = (kappa0 - A) t1_0 + (beta0 - B) t2_0 + sum_{m>=1} delta^m (-A t1_m - B t2_m),
+    //           with a1 = -A delta^m, b1 = -B delta^m (FP64)
+    //  generic: acc = -kappa sum_{s=1..M} delta^s t_s (a1 = delta^s), b1 = IDFT(u_hat)
+    double acc[E], a1[E], b1[E];
+    cpx<T> y[E];
 #pragma unroll
-        for (int e = 0; e < E; ++e) y[e] = hermitian_pair<T, N, W>(h1, h2, c, t + TP * e);
-        __syncthreads();
+    for (int e = 0; e < E; ++e) {
+        acc[e] = 0.0;
+        a1[e] = 1.0;
+        b1[e] = 0.0;
+    }
+    if constexpr (MODE == C2R_KICK) {
+        const T* Ap = a.A + (long long)item * a.coef_stride + colc;
+        const T* Bp = a.B + (long long)item * a.coef_stride + colc;
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+            const long long off = (long long)(t + TP * e) * a.inner;
+            a1[e] = -double(Ap[off]);
+            b1[e] = -double(Bp[off]);
+        }
+    }
+
+    load_pair(0);
+    for (int tr = 0; tr < nT; ++tr) {
+        build(y);
+        if (tr + 1 < nT) load_pair(tr + 1);  // in flight during the transform
         fft_pencil<T, N, E, +1>(y, t, lds, a.tw);
+        if constexpr (MODE == C2R_APPLY) {
+#pragma unroll
+            for (int e = 0; e < E; ++e) {
+                const double d = dptr[(long long)(t + TP * e) * a.inner];
+                acc[e] += a1[e] * (double(y[e].x) + d * double(y[e].y));
+                a1[e] *= d * d;
+            }
+        } else if constexpr (MODE == C2R_KICK) {
+            const double k0c = (tr == 0) ? sc.kappa0 : 0.0;
+            const double b0c = (tr == 0) ? sc.beta0 : 0.0;
+#pragma unroll
+            for (int e = 0; e < E; ++e) {
+                const double d = dptr[(long long)(t + TP * e) * a.inner];
+                acc[e] += (k0c + a1[e]) * double(y[e].x) + (b0c + b1[e]) * double(y[e].y);
+                a1[e] *= d;
+                b1[e] *= d;
+            }
+        } else if constexpr (MODE == C2R_KICK_GENERIC) {
+#pragma unroll
+            for (int e = 0; e < E; ++e) {
+                const double d = dptr[(long long)(t + TP * e) * a.inner];
+                for (int h = 0; h < 2; ++h) {
+                    const int sidx = 2 * tr + h;
+                    if (sidx >= nS) break;
+                    const double val = h == 0 ? double(y[e].x) : double(y[e].y);
+                    if (sidx == a.M + 1) {
+                        b1[e] = val;
+                    } else {
+                        if (sidx > 0) acc[e] -= sc.kappa0 * a1[e] * val;
+                        a1[e] *= d;
+                    }
+                }
+            }
+        }
+    }
+
+    if constexpr (MODE == C2R_EXPORT) {
         if (active) {
             T* u = a.r0 + (long long)item * a.Nreal + colc;
             T* v = a.r1 + (long long)item * a.Nreal + colc;
@@ -488,32 +587,7 @@ __global__ __launch_bounds__(W*(N / E)) void k_c2r0(C2RArgs<T> a) {
         }
         return;
     }
-
-    if (a.mode == C2R_APPLY) {
-        // slots m (real part) and m+1 (imaginary part) in one transform
-        double acc[E], dp[E];
-#pragma unroll
-        for (int e = 0; e < E; ++e) {
-            acc[e] = 0.0;
-            dp[e] = 1.0;
-        }
-        for (int m = 0; m <= a.M; m += 2) {
-            const bool pair = (m + 1 <= a.M);
-            stage(m, pair ? m + 1 : -1);
-            cpx<T> y[E];
-#pragma unroll
-            for (int e = 0; e < E; ++e)
-                y[e] = hermitian_pair<T, N, W>(h1, pair ? h2 : nullptr, c, t + TP * e);
-            __syncthreads();
-            fft_pencil<T, N, E, +1>(y, t, lds, a.tw);
-            if (num_stages(N, E) < 2) __syncthreads();
-#pragma unroll
-            for (int e = 0; e < E; ++e) {
-                const double d = dptr[(long long)(t + TP * e) * a.inner];
-                acc[e] += dp[e] * (double(y[e].x) + d * double(y[e].y));
-                dp[e] *= d * d;
-            }
-        }
+    if constexpr (MODE == C2R_APPLY) {
         if (active) {
             T* o = a.r0 + (long long)item * a.Nreal + colc;
 #pragma unroll
@@ -521,114 +595,17 @@ __global__ __launch_bounds__(W*(N / E)) void k_c2r0(C2RArgs<T> a) {
         }
         return;
     }
-
-    if (a.mode == C2R_KICK_GENERIC) {
-        // slots s = 0..M: l_s |mu|^{2 s0} u_hat, slot M+1: u_hat; pairs (s, s+1) share
-        // one transform. dv = -kappa sum_{s=1..M} delta^s t_s + lambda u^3.
-        const SolveScalars sc = a.sc[item * a.sc_stride];
-        double acc[E], dp[E], uu[E];
-#pragma unroll
-        for (int e = 0; e < E; ++e) {
-            acc[e] = 0.0;
-            dp[e] = 1.0;
-            uu[e] = 0.0;
-        }
-        const int ns = a.M + 2;
-        for (int s0 = 0; s0 < ns; s0 += 2) {
-            const bool pair = (s0 + 1 < ns);
-            stage(s0, pair ? s0 + 1 : -1);
-            cpx<T> y[E];
-#pragma unroll
-            for (int e = 0; e < E; ++e)
-                y[e] = hermitian_pair<T, N, W>(h1, pair ? h2 : nullptr, c, t + TP * e);
-            __syncthreads();
-            fft_pencil<T, N, E, +1>(y, t, lds, a.tw);
-            if (num_stages(N, E) < 2) __syncthreads();
-#pragma unroll
-            for (int e = 0; e < E; ++e) {
-                const double d = dptr[(long long)(t + TP * e) * a.inner];
-                for (int h = 0; h < 2; ++h) {
-                    const int sidx = s0 + h;
-                    if (sidx >= ns) break;
-                    const double val = h == 0 ? double(y[e].x) : double(y[e].y);
-                    if (sidx == a.M + 1) {
-                        uu[e] = val;
-                    } else {
-                        if (sidx > 0) acc[e] -= sc.kappa0 * dp[e] * val;
-                        dp[e] *= d;
-                    }
-                }
-            }
-        }
-        cpx<T> z[E];
-        bool bad = false;
-#pragma unroll
-        for (int e = 0; e < E; ++e) {
-            const double dv = acc[e] + sc.lambda * uu[e] * uu[e] * uu[e];
-            bad |= !isfinite(dv);
-            z[e] = {T(dv), T(0)};
-        }
-        if (bad && active) a.flag[0] = 1;
-        fft_pencil<T, N, E, -1>(z, t, lds, a.tw);
-        if (active) {
-            cpx<T>* dst = a.dv_out + (long long)item * a.istride + colc;
-#pragma unroll
-            for (int e = 0; e < E; ++e) {
-                const int k = t + TP * e;
-                if (k <= N / 2) {
-                    cpx<T> w = z[e];
-                    if (k == 0 || k == N / 2) w.y = T(0);
-                    dst[(long long)k * a.inner] = w;
-                }
-            }
-        }
-        return;
-    }
-
-    // C2R_KICK: slots 2m (|mu|^{2 sig1} u_hat terms) and 2m+1 (|mu|^{2 sig2} v_hat terms).
-    // dv = (kappa0 - A) t1_0 + (beta0 - B) t2_0 + sum_{m>=1} delta^m (-A t1_m - B t2_m),
-    // with running coefficients a1 = -A delta^m, b1 = -B delta^m (FP64).
-    const SolveScalars sc = a.sc[item * a.sc_stride];
-    double acc[E], a1[E], b1[E];
-    {
-        const T* Ap = a.A + (long long)item * a.coef_stride + colc;
-        const T* Bp = a.B + (long long)item * a.coef_stride + colc;
-#pragma unroll
-        for (int e = 0; e < E; ++e) {
-            const long long off = (long long)(t + TP * e) * a.inner;
-            a1[e] = -double(Ap[off]);
-            b1[e] = -double(Bp[off]);
-            acc[e] = 0.0;
-        }
-    }
-    for (int m = 0; m <= a.M; ++m) {
-        stage(2 * m, 2 * m + 1);
-        cpx<T> y[E];
-#pragma unroll
-        for (int e = 0; e < E; ++e) y[e] = hermitian_pair<T, N, W>(h1, h2, c, t + TP * e);
-        __syncthreads();
-        fft_pencil<T, N, E, +1>(y, t, lds, a.tw);
-        if (num_stages(N, E) < 2) __syncthreads();
-        const double k0c = (m == 0) ? sc.kappa0 : 0.0;
-        const double b0c = (m == 0) ? sc.beta0 : 0.0;
-#pragma unroll
-        for (int e = 0; e < E; ++e) {
-            const double d = dptr[(long long)(t + TP * e) * a.inner];
-            acc[e] += (k0c + a1[e]) * double(y[e].x) + (b0c + b1[e]) * double(y[e].y);
-            a1[e] *= d;
-            b1[e] *= d;
-        }
-    }
+    // kick: right-hand side, finiteness flag, forward axis-0 transform, half rows out
     cpx<T> z[E];
-    {
-        bool bad = false;
+    bool bad = false;
 #pragma unroll
-        for (int e = 0; e < E; ++e) {
-            bad |= !isfinite(acc[e]);
-            z[e] = {T(acc[e]), T(0)};
-        }
-        if (bad && active) a.flag[0] = 1;
+    for (int e = 0; e < E; ++e) {
+        double dv = acc[e];
+        if constexpr (MODE == C2R_KICK_GENERIC) dv += sc.lambda * b1[e] * b1[e] * b1[e];
+        bad |= !isfinite(dv);
+        z[e] = {T(dv), T(0)};
     }
+    if (bad && active) a.flag[0] = 1;
     fft_pencil<T, N, E, -1>(z, t, lds, a.tw);
     if (active) {
         cpx<T>* dst = a.dv_out + (long long)item * a.istride + colc;

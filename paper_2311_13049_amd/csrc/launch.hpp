@@ -24,13 +24,16 @@ struct Launch {
     static bool supported_1d(int N);
     static int tile_w(int N);
     static int c2r_w(int N);
+    static int c2r_tile(int N, int variant);
     template <typename TI>
     static hipError_t contig(int N, const ContigArgs<T, TI>& a, int items, hipStream_t s);
     static hipError_t mid(int N, int dir, const MidArgs<T>& a, int planes, int items, hipStream_t s);
     // forward axis-0 transform of real T data into FP64 half spectra
     static hipError_t r2c0(int N, const R2CArgs<T>& a, int items, hipStream_t s);
     static int r2c0_w(int N);
-    static hipError_t c2r0(int N, const C2RArgs<T>& a, int items, hipStream_t s);
+    // variant 0: W columns x 8 elements per thread; 1: W x 16 (fewer threads
+    // per workgroup); 2: W/2 x 8 (W = c2r_width)
+    static hipError_t c2r0(int N, const C2RArgs<T>& a, int items, hipStream_t s, int variant = 0);
     static hipError_t d1_apply(int N, const Args1D<T>& a, int items, hipStream_t s);
     static hipError_t d1_step(int N, const Args1D<T>& a, int items, hipStream_t s);
 };

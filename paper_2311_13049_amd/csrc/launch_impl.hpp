@@ -111,19 +111,50 @@ hipError_t Launch<T>::r2c0(int N, const R2CArgs<T>& a, int items, hipStream_t s)
     }
 }
 
+template <typename T, int n, int E, int W>
+hipError_t c2r0_mode(const C2RArgs<T>& a, int items, hipStream_t s) {
+    const dim3 block(W * (n / E));
+    const dim3 grid((a.inner + W - 1) / W, items);
+    switch (a.mode) {
+        case C2R_APPLY: k_c2r0<T, n, E, W, C2R_APPLY><<<grid, block, 0, s>>>(a); break;
+        case C2R_KICK: k_c2r0<T, n, E, W, C2R_KICK><<<grid, block, 0, s>>>(a); break;
+        case C2R_EXPORT: k_c2r0<T, n, E, W, C2R_EXPORT><<<grid, block, 0, s>>>(a); break;
+        case C2R_KICK_GENERIC: k_c2r0<T, n, E, W, C2R_KICK_GENERIC><<<grid, block, 0, s>>>(a); break;
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+// variants: 0 -> (W, 8), 1 -> (W, 16), 2 -> (W/2, 8) with W = c2r_width
 template <typename T>
-hipError_t Launch<T>::c2r0(int N, const C2RArgs<T>& a, int items, hipStream_t s) {
+hipError_t Launch<T>::c2r0(int N, const C2RArgs<T>& a, int items, hipStream_t s, int variant) {
     switch (N) {
 #define C_(n)                                                                           \
     case n: {                                                                           \
-        constexpr int W = c2r_width<T, n>(), E = e_c2r0(n);                                   \
-        dim3 grid((a.inner + W - 1) / W, items);                                        \
-        k_c2r0<T, n, E, W><<<grid, dim3(W * (n / E)), 0, s>>>(a);                       \
-        return hipGetLastError();                                                       \
+        constexpr int W = c2r_width<T, n>(), E = e_c2r0(n);                             \
+        constexpr int E2 = (n >= 16) ? 16 : E;                                          \
+        constexpr int W2 = (W >= 8) ? W / 2 : W;                                        \
+        if (variant == 1 && E2 != E) return c2r0_mode<T, n, E2, W>(a, items, s);        \
+        if (variant == 2 && W2 != W) return c2r0_mode<T, n, E, W2>(a, items, s);        \
+        return c2r0_mode<T, n, E, W>(a, items, s);                                      \
     }
         VOFL_MULTI_SIZES(C_)
 #undef C_
         default: return hipErrorInvalidValue;
+    }
+}
+
+template <typename T>
+int Launch<T>::c2r_tile(int N, int variant) {
+    switch (N) {
+#define C_(n)                                                                           \
+    case n: {                                                                           \
+        constexpr int W = c2r_width<T, n>();                                            \
+        return (variant == 2 && W >= 8) ? W / 2 : W;                                    \
+    }
+        VOFL_MULTI_SIZES(C_)
+#undef C_
+        default: return 0;
     }
 }
 

@@ -16,6 +16,7 @@
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <map>
 #include <string>
@@ -192,6 +193,7 @@ struct vofl_plan_s {
     void* work = nullptr;
     int* flag = nullptr;
     std::vector<void*> allocs;
+    int c2r_variant = 0;               // k_c2r0 elements-per-thread variant
     hipStream_t own_stream = nullptr;  // used by vofl_step_batch
     hipEvent_t fork_ev = nullptr, join_ev = nullptr;
     // timing
@@ -357,8 +359,8 @@ ContigArgs<T, TI> contig_base(vofl_plan_s* p) {
 
 // 3D middle-axis transform of nf fields per item (item stride istride)
 template <typename T>
-hipError_t mid(vofl_plan_s* p, int dir, cpx<T>* buf, long long istride, int nf, int items,
-               const cpx<T>* tw, hipStream_t s) {
+hipError_t mid(vofl_plan_s* p, const char* name, int dir, cpx<T>* buf, long long istride, int nf,
+               int items, const cpx<T>* tw, hipStream_t s) {
     const Geometry& g = p->g;
     if (g.ndim != 3) return hipSuccess;
     MidArgs<T> m{};
@@ -370,7 +372,7 @@ hipError_t mid(vofl_plan_s* p, int dir, cpx<T>* buf, long long istride, int nf, 
     const int W = Launch<T>::tile_w(g.n[1]);
     m.tiles_per_plane = (g.n[2] + W - 1) / W;
     m.tw = tw;
-    return p->timed("mid", s, [&] { return Launch<T>::mid(g.n[1], dir, m, g.n0h, items, s); });
+    return p->timed(name, s, [&] { return Launch<T>::mid(g.n[1], dir, m, g.n0h, items, s); });
 }
 
 // forward transform of real fields (items of Nreal values) into the FP64
@@ -417,7 +419,7 @@ int apply_multi(vofl_plan_s* p, int op, const T* u, T* out, int nf, hipStream_t 
     cpx<double>* stage = (cpx<double>*)p->U;
     hipError_t e = forward_to_stage<T>(p, u, stage, nf, s);
     if (e != hipSuccess) return hip_fail(e, "r2c0 launch");
-    if ((e = mid<double>(p, -1, stage, g.H, 1, nf, p->tw64[1 % g.ndim], s)) != hipSuccess)
+    if ((e = mid<double>(p, "mid_apply_fwd", -1, stage, g.H, 1, nf, p->tw64[1 % g.ndim], s)) != hipSuccess)
         return hip_fail(e, "mid launch");
     ContigArgs<T, double> a = contig_base<T, double>(p);
     a.in = stage;
@@ -432,14 +434,14 @@ int apply_multi(vofl_plan_s* p, int op, const T* u, T* out, int nf, hipStream_t 
     a.op = op;
     e = p->timed("contig_apply", s, [&] { return Launch<T>::contig(g.nlast, a, nf, s); });
     if (e != hipSuccess) return hip_fail(e, "contig launch");
-    if ((e = mid<T>(p, +1, W, AS, p->M + 1, nf, (const cpx<T>*)p->tw[1 % g.ndim], s)) != hipSuccess)
+    if ((e = mid<T>(p, "mid_apply_terms", +1, W, AS, p->M + 1, nf, (const cpx<T>*)p->tw[1 % g.ndim], s)) != hipSuccess)
         return hip_fail(e, "mid launch");
     C2RArgs<T> c = c2r_base<T>(p);
     c.in = W;
     c.istride = AS;
     c.mode = C2R_APPLY;
     c.r0 = out;
-    e = p->timed("c2r0_apply", s, [&] { return Launch<T>::c2r0(g.n[0], c, nf, s); });
+    e = p->timed("c2r0_apply", s, [&] { return Launch<T>::c2r0(g.n[0], c, nf, s, p->c2r_variant); });
     if (e != hipSuccess) return hip_fail(e, "c2r0 launch");
     return VOFL_OK;
 }
@@ -464,7 +466,7 @@ int step_multi(vofl_plan_s* p, T* u, T* v, int nsteps, hipStream_t s) {
     // first half step of the exact part and the first terms
     if ((e = forward_to_stage<T>(p, u, U, items, s)) != hipSuccess) return hip_fail(e, "r2c0 launch");
     if ((e = forward_to_stage<T>(p, v, V, items, s)) != hipSuccess) return hip_fail(e, "r2c0 launch");
-    if ((e = mid<double>(p, -1, U, g.H, 1, 2 * items, p->tw64[1 % g.ndim], s)) != hipSuccess)
+    if ((e = mid<double>(p, "mid_init", -1, U, g.H, 1, 2 * items, p->tw64[1 % g.ndim], s)) != hipSuccess)
         return hip_fail(e, "mid launch");
     {
         ContigArgs<T, double> a = contig_base<T, double>(p);
@@ -500,10 +502,10 @@ int step_multi(vofl_plan_s* p, T* u, T* v, int nsteps, hipStream_t s) {
 
     for (int st = 0; st < nsteps; ++st) {
         const bool last = (st + 1 == nsteps);
-        if ((e = mid<T>(p, +1, W, SS, nterm, items, twm, s)) != hipSuccess) return hip_fail(e, "mid launch");
-        e = p->timed("c2r0_kick", s, [&] { return Launch<T>::c2r0(g.n[0], c, items, s); });
+        if ((e = mid<T>(p, "mid_terms", +1, W, SS, nterm, items, twm, s)) != hipSuccess) return hip_fail(e, "mid launch");
+        e = p->timed("c2r0_kick", s, [&] { return Launch<T>::c2r0(g.n[0], c, items, s, p->c2r_variant); });
         if (e != hipSuccess) return hip_fail(e, "c2r0 launch");
-        if ((e = mid<T>(p, -1, W + (long long)dv * g.H, SS, 1, items, twm, s)) != hipSuccess)
+        if ((e = mid<T>(p, "mid_dv", -1, W + (long long)dv * g.H, SS, 1, items, twm, s)) != hipSuccess)
             return hip_fail(e, "mid launch");
         a.tprop = last ? 0.5 * p->dt : p->dt;
         a.emit_kind = last ? EMIT_EXPORT : emit_terms;
@@ -511,7 +513,7 @@ int step_multi(vofl_plan_s* p, T* u, T* v, int nsteps, hipStream_t s) {
         e = p->timed("contig_kick", s, [&] { return Launch<T>::contig(g.nlast, a, items, s); });
         if (e != hipSuccess) return hip_fail(e, "contig launch");
     }
-    if ((e = mid<T>(p, +1, W + (long long)h0 * g.H, SS, 2, items, twm, s)) != hipSuccess)
+    if ((e = mid<T>(p, "mid_export", +1, W + (long long)h0 * g.H, SS, 2, items, twm, s)) != hipSuccess)
         return hip_fail(e, "mid launch");
     C2RArgs<T> x = c2r_base<T>(p);
     x.in = W + (long long)h0 * g.H;
@@ -519,7 +521,7 @@ int step_multi(vofl_plan_s* p, T* u, T* v, int nsteps, hipStream_t s) {
     x.mode = C2R_EXPORT;
     x.r0 = u;
     x.r1 = v;
-    e = p->timed("c2r0_export", s, [&] { return Launch<T>::c2r0(g.n[0], x, items, s); });
+    e = p->timed("c2r0_export", s, [&] { return Launch<T>::c2r0(g.n[0], x, items, s, p->c2r_variant); });
     if (e != hipSuccess) return hip_fail(e, "c2r0 launch");
     return VOFL_OK;
 }
@@ -659,6 +661,7 @@ int vofl_plan(const vofl_desc* d, void* stream, vofl_plan_t* out) {
         p->hi[i] = d->hi[i];
     }
     p->sc_host = sc;
+    if (const char* ev = std::getenv("VOFL_C2R_VARIANT")) p->c2r_variant = std::atoi(ev);
     rc = (d->precision == VOFL_FP32) ? upload_tables<float>(p, delta, A, B)
                                      : upload_tables<double>(p, delta, A, B);
     if (rc) {
