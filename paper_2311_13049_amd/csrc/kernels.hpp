@@ -108,6 +108,15 @@ constexpr int c2r_width() {
     return w < lim ? w : lim;
 }
 
+// Copy a length-N twiddle table into LDS (called by every thread before
+// any transform; ends with a barrier). Reading twiddles from LDS keeps the
+// FFT stages from waiting on outstanding global loads.
+template <typename T, int N>
+__device__ __forceinline__ void stage_twiddles(cpx<T>* dst, const cpx<T>* __restrict__ src) {
+    for (int i = threadIdx.x; i < N; i += blockDim.x) dst[i] = src[i];
+    __syncthreads();
+}
+
 // ---------------------------------------------------------------------------
 // k_contig: last-axis pencils
 // ---------------------------------------------------------------------------
@@ -142,6 +151,10 @@ __global__ __launch_bounds__(P*(N / E)) void k_contig(ContigArgs<T, TI> a) {
     constexpr int FPI = LdsPencil<TI>::footprint(N);
     constexpr int FP = LdsPencil<T>::footprint(N);
     __shared__ cpx<TI> lds_raw[P * FPI];  // holds P pencils of TI (>= size of T)
+    __shared__ cpx<TI> twi_s[N];
+    __shared__ cpx<T> tw_s[N];
+    stage_twiddles<TI, N>(twi_s, a.tw_in);
+    stage_twiddles<T, N>(tw_s, a.tw);
     const int lp = threadIdx.x / TP;
     const int t = threadIdx.x % TP;
     const int p = blockIdx.x * P + lp;
@@ -162,7 +175,7 @@ __global__ __launch_bounds__(P*(N / E)) void k_contig(ContigArgs<T, TI> a) {
         const cpx<TI>* src = a.in + (long long)bi * a.in_istride + pen;
 #pragma unroll
         for (int e = 0; e < E; ++e) d[e] = src[t + TP * e];
-        fft_pencil<TI, N, E, -1>(d, t, ldsi, a.tw_in);
+        fft_pencil<TI, N, E, -1>(d, t, ldsi, twi_s);
         const cpx<double>* Us = a.U + (long long)bi * a.H + pen;
         const cpx<double>* Vs = a.V + (long long)bi * a.H + pen;
         const double s = a.dt * a.invN;
@@ -178,7 +191,7 @@ __global__ __launch_bounds__(P*(N / E)) void k_contig(ContigArgs<T, TI> a) {
             const cpx<TI>* src = a.in + (long long)bi * a.in_istride + (long long)f * a.in_fstride + pen;
 #pragma unroll
             for (int e = 0; e < E; ++e) d[e] = src[t + TP * e];
-            fft_pencil<TI, N, E, -1>(d, t, ldsi, a.tw_in);
+            fft_pencil<TI, N, E, -1>(d, t, ldsi, twi_s);
 #pragma unroll
             for (int e = 0; e < E; ++e) {
                 const cpx<double> z = {double(d[e].x) * a.invN, double(d[e].y) * a.invN};
@@ -238,7 +251,7 @@ __global__ __launch_bounds__(P*(N / E)) void k_contig(ContigArgs<T, TI> a) {
             cpx<T> x[E];
 #pragma unroll
             for (int e = 0; e < E; ++e) x[e] = from_d<T>(vh[e]);
-            fft_pencil<T, N, E, +1>(x, t, lds, a.tw);
+            fft_pencil<T, N, E, +1>(x, t, lds, tw_s);
             if (active) {
                 cpx<T>* d = dst0 + (long long)(a.M + 1) * a.H;
 #pragma unroll
@@ -252,7 +265,7 @@ __global__ __launch_bounds__(P*(N / E)) void k_contig(ContigArgs<T, TI> a) {
             cpx<T> x[E];
 #pragma unroll
             for (int e = 0; e < E; ++e) x[e] = from_d<T>(uh[e]);
-            fft_pencil<T, N, E, +1>(x, t, lds, a.tw);
+            fft_pencil<T, N, E, +1>(x, t, lds, tw_s);
             if (active) {
                 cpx<T>* d = dst0 + (long long)m * a.H;
 #pragma unroll
@@ -270,7 +283,7 @@ __global__ __launch_bounds__(P*(N / E)) void k_contig(ContigArgs<T, TI> a) {
             cpx<T> x[E];
 #pragma unroll
             for (int e = 0; e < E; ++e) x[e] = from_d<T>(uh[e]);
-            fft_pencil<T, N, E, +1>(x, t, lds, a.tw);
+            fft_pencil<T, N, E, +1>(x, t, lds, tw_s);
             if (active) {
                 cpx<T>* d = dst0 + (long long)(2 * m) * a.H;
 #pragma unroll
@@ -278,7 +291,7 @@ __global__ __launch_bounds__(P*(N / E)) void k_contig(ContigArgs<T, TI> a) {
             }
 #pragma unroll
             for (int e = 0; e < E; ++e) x[e] = from_d<T>(vh[e]);
-            fft_pencil<T, N, E, +1>(x, t, lds, a.tw);
+            fft_pencil<T, N, E, +1>(x, t, lds, tw_s);
             if (active) {
                 cpx<T>* d = dst0 + (long long)(2 * m + 1) * a.H;
 #pragma unroll
@@ -297,7 +310,7 @@ __global__ __launch_bounds__(P*(N / E)) void k_contig(ContigArgs<T, TI> a) {
             cpx<T> x[E];
 #pragma unroll
             for (int e = 0; e < E; ++e) x[e] = from_d<T>(f == 0 ? uh[e] : vh[e]);
-            fft_pencil<T, N, E, +1>(x, t, lds, a.tw);
+            fft_pencil<T, N, E, +1>(x, t, lds, tw_s);
             if (active) {
                 cpx<T>* d = dst0 + (long long)f * a.H;
 #pragma unroll
@@ -325,6 +338,8 @@ template <typename T, int N, int E, int W, int DIR>
 __global__ __launch_bounds__(W*(N / E)) void k_mid(MidArgs<T> a) {
     constexpr int TP = N / E;
     __shared__ cpx<T> lds_raw[N * W];
+    __shared__ cpx<T> tw_s[N];
+    stage_twiddles<T, N>(tw_s, a.tw);
     const int c = threadIdx.x % W;
     const int t = threadIdx.x / W;
     const int plane = blockIdx.x / a.tiles_per_plane;
@@ -339,7 +354,7 @@ __global__ __launch_bounds__(W*(N / E)) void k_mid(MidArgs<T> a) {
     cpx<T> v[E];
 #pragma unroll
     for (int e = 0; e < E; ++e) v[e] = base[(long long)(t + TP * e) * a.n2];
-    fft_pencil<T, N, E, DIR>(v, t, lds, a.tw);
+    fft_pencil<T, N, E, DIR>(v, t, lds, tw_s);
     if (active) {
 #pragma unroll
         for (int e = 0; e < E; ++e) base[(long long)(t + TP * e) * a.n2] = v[e];
@@ -366,6 +381,8 @@ template <typename TR, int N, int E, int W>
 __global__ __launch_bounds__(W*(N / E)) void k_r2c0(R2CArgs<TR> a) {
     constexpr int TP = N / E;
     __shared__ cpx<double> lds_raw[N * W];
+    __shared__ cpx<double> tw_s[N];
+    stage_twiddles<double, N>(tw_s, a.tw);
     const int c = threadIdx.x % W;
     const int t = threadIdx.x / W;
     const int col = blockIdx.x * W + c;
@@ -377,7 +394,7 @@ __global__ __launch_bounds__(W*(N / E)) void k_r2c0(R2CArgs<TR> a) {
     cpx<double> v[E];
 #pragma unroll
     for (int e = 0; e < E; ++e) v[e] = {double(src[(long long)(t + TP * e) * a.inner]), 0.0};
-    fft_pencil<double, N, E, -1>(v, t, lds, a.tw);
+    fft_pencil<double, N, E, -1>(v, t, lds, tw_s);
     if (active) {
         cpx<double>* dst = a.out + (long long)item * a.H + colc;
 #pragma unroll
@@ -460,6 +477,8 @@ __global__ __launch_bounds__(W*(N / E)) void k_c2r0(C2RArgs<T> a) {
     static_assert(MODE >= 0 && MODE <= 3, "mode");
     constexpr int TP = N / E;
     __shared__ cpx<T> lds_fft[N * W];
+    __shared__ cpx<T> tw_s[N];
+    stage_twiddles<T, N>(tw_s, a.tw);
     const int c = threadIdx.x % W;
     const int t = threadIdx.x / W;
     const int col = blockIdx.x * W + c;
@@ -538,7 +557,7 @@ __global__ __launch_bounds__(W*(N / E)) void k_c2r0(C2RArgs<T> a) {
     for (int tr = 0; tr < nT; ++tr) {
         build(y);
         if (tr + 1 < nT) load_pair(tr + 1);  // in flight during the transform
-        fft_pencil<T, N, E, +1>(y, t, lds, a.tw);
+        fft_pencil<T, N, E, +1>(y, t, lds, tw_s);
         if constexpr (MODE == C2R_APPLY) {
 #pragma unroll
             for (int e = 0; e < E; ++e) {
@@ -606,7 +625,7 @@ __global__ __launch_bounds__(W*(N / E)) void k_c2r0(C2RArgs<T> a) {
         z[e] = {T(dv), T(0)};
     }
     if (bad && active) a.flag[0] = 1;
-    fft_pencil<T, N, E, -1>(z, t, lds, a.tw);
+    fft_pencil<T, N, E, -1>(z, t, lds, tw_s);
     if (active) {
         cpx<T>* dst = a.dv_out + (long long)item * a.istride + colc;
 #pragma unroll
@@ -651,6 +670,19 @@ __global__ __launch_bounds__(N / E) void k_1d_apply(Args1D<T> a) {
     __shared__ cpx<double> lds_raw[LdsPencil<double>::footprint(N)];
     const LdsPencil<double> lds64{lds_raw};
     const LdsPencil<T> lds{reinterpret_cast<cpx<T>*>(lds_raw)};
+    // twiddles from LDS up to N = 1024; longer 1D transforms read them from
+    // global memory (the tables would not fit next to the data)
+    constexpr int NTW = (N <= 1024) ? N : 1;
+    __shared__ cpx<double> tw64_l[NTW];
+    __shared__ cpx<T> tw_l[NTW];
+    const cpx<double>* tw64_s = a.tw64;
+    const cpx<T>* tw_s = a.tw;
+    if constexpr (N <= 1024) {
+        stage_twiddles<double, N>(tw64_l, a.tw64);
+        stage_twiddles<T, N>(tw_l, a.tw);
+        tw64_s = tw64_l;
+        tw_s = tw_l;
+    }
     const int t = threadIdx.x;
     const int item = blockIdx.x;
     const SolveScalars sc = a.sc[item * a.sc_stride];
@@ -658,7 +690,7 @@ __global__ __launch_bounds__(N / E) void k_1d_apply(Args1D<T> a) {
     cpx<double> x[E];  // forward transform of the input in FP64
 #pragma unroll
     for (int e = 0; e < E; ++e) x[e] = {double(u[t + TP * e]), 0.0};
-    fft_pencil<double, N, E, -1>(x, t, lds64, a.tw64);
+    fft_pencil<double, N, E, -1>(x, t, lds64, tw64_s);
     const double sig = (a.op == 2) ? sc.sig2 : sc.sig1;
     cpx<double> r[E];
     double L[E], dl[E], acc[E], dp[E];
@@ -689,7 +721,7 @@ __global__ __launch_bounds__(N / E) void k_1d_apply(Args1D<T> a) {
             const double g = pair ? L[e] / double(m + 2) : 0.0;
             r[e] = {x1.x * g, x1.y * g};
         }
-        fft_pencil<T, N, E, +1>(y, t, lds, a.tw);
+        fft_pencil<T, N, E, +1>(y, t, lds, tw_s);
 #pragma unroll
         for (int e = 0; e < E; ++e) {
             acc[e] += dp[e] * (double(y[e].x) + dl[e] * double(y[e].y));
@@ -720,6 +752,19 @@ __global__ __launch_bounds__(N / E) void k_1d_step(Args1D<T> a) {
     __shared__ cpx<double> lds_raw[LdsPencil<double>::footprint(N)];
     const LdsPencil<double> lds64{lds_raw};
     const LdsPencil<T> lds{reinterpret_cast<cpx<T>*>(lds_raw)};
+    // twiddles from LDS up to N = 1024; longer 1D transforms read them from
+    // global memory (the tables would not fit next to the data)
+    constexpr int NTW = (N <= 1024) ? N : 1;
+    __shared__ cpx<double> tw64_l[NTW];
+    __shared__ cpx<T> tw_l[NTW];
+    const cpx<double>* tw64_s = a.tw64;
+    const cpx<T>* tw_s = a.tw;
+    if constexpr (N <= 1024) {
+        stage_twiddles<double, N>(tw64_l, a.tw64);
+        stage_twiddles<T, N>(tw_l, a.tw);
+        tw64_s = tw64_l;
+        tw_s = tw_l;
+    }
     const int t = threadIdx.x;
     const int item = blockIdx.x;
     const SolveScalars sc = a.sc[item * a.sc_stride];
@@ -730,13 +775,13 @@ __global__ __launch_bounds__(N / E) void k_1d_step(Args1D<T> a) {
         const T* u = a.u_in + (long long)item * N;
 #pragma unroll
         for (int e = 0; e < E; ++e) x[e] = {double(u[t + TP * e]), 0.0};
-        fft_pencil<double, N, E, -1>(x, t, lds64, a.tw64);
+        fft_pencil<double, N, E, -1>(x, t, lds64, tw64_s);
 #pragma unroll
         for (int e = 0; e < E; ++e) uh[e] = {x[e].x * a.invN, x[e].y * a.invN};
         const T* v = a.v_in + (long long)item * N;
 #pragma unroll
         for (int e = 0; e < E; ++e) x[e] = {double(v[t + TP * e]), 0.0};
-        fft_pencil<double, N, E, -1>(x, t, lds64, a.tw64);
+        fft_pencil<double, N, E, -1>(x, t, lds64, tw64_s);
 #pragma unroll
         for (int e = 0; e < E; ++e) vh[e] = {x[e].x * a.invN, x[e].y * a.invN};
     }
@@ -785,7 +830,7 @@ __global__ __launch_bounds__(N / E) void k_1d_step(Args1D<T> a) {
                     }
                     y[e] = {T(xs[0].x - xs[1].y), T(xs[0].y + xs[1].x)};
                 }
-                fft_pencil<T, N, E, +1>(y, t, lds, a.tw);
+                fft_pencil<T, N, E, +1>(y, t, lds, tw_s);
 #pragma unroll
                 for (int e = 0; e < E; ++e) {
                     const int k = t + TP * e;
@@ -820,7 +865,7 @@ __global__ __launch_bounds__(N / E) void k_1d_step(Args1D<T> a) {
             }
             double lm = 1.0;  // running 1/m! for the multipliers
             for (int m = 0; m <= a.M; ++m) {
-                fft_pencil<T, N, E, +1>(y, t, lds, a.tw);
+                fft_pencil<T, N, E, +1>(y, t, lds, tw_s);
                 const double k0c = (m == 0) ? sc.kappa0 : 0.0;
                 const double b0c = (m == 0) ? sc.beta0 : 0.0;
 #pragma unroll
@@ -853,7 +898,7 @@ __global__ __launch_bounds__(N / E) void k_1d_step(Args1D<T> a) {
             bad |= !isfinite(acc[e]);
             z[e] = {T(acc[e]), T(0)};
         }
-        fft_pencil<T, N, E, -1>(z, t, lds, a.tw);
+        fft_pencil<T, N, E, -1>(z, t, lds, tw_s);
         const double sc2 = a.dt * a.invN;
 #pragma unroll
         for (int e = 0; e < E; ++e) vh[e] = {vh[e].x + sc2 * double(z[e].x), vh[e].y + sc2 * double(z[e].y)};
@@ -863,7 +908,7 @@ __global__ __launch_bounds__(N / E) void k_1d_step(Args1D<T> a) {
     cpx<T> y[E];
 #pragma unroll
     for (int e = 0; e < E; ++e) y[e] = {T(uh[e].x - vh[e].y), T(uh[e].y + vh[e].x)};
-    fft_pencil<T, N, E, +1>(y, t, lds, a.tw);
+    fft_pencil<T, N, E, +1>(y, t, lds, tw_s);
     T* uo = a.u_out + (long long)item * N;
     T* vo = a.v_out + (long long)item * N;
 #pragma unroll
