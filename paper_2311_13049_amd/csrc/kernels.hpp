@@ -342,8 +342,9 @@ __global__ __launch_bounds__(W*(N / E)) void k_mid(MidArgs<T> a) {
     stage_twiddles<T, N>(tw_s, a.tw);
     const int c = threadIdx.x % W;
     const int t = threadIdx.x / W;
-    const int plane = blockIdx.x / a.tiles_per_plane;
-    const int col = (blockIdx.x % a.tiles_per_plane) * W + c;
+    const int tiles = (a.n2 + W - 1) / W;
+    const int plane = blockIdx.x / tiles;
+    const int col = (blockIdx.x % tiles) * W + c;
     const bool active = col < a.n2;
     const int colc = active ? col : 0;
     const int item = blockIdx.y / a.nf;
@@ -525,9 +526,14 @@ __global__ __launch_bounds__(W*(N / E)) void k_c2r0(C2RArgs<T> a) {
         }
     };
 
-    // delta at this thread's points (re-read from cache where needed)
+    // delta at this thread's points, held in registers (FP64)
     const double* dptr = a.delta + (long long)item * a.coef_stride + colc;
     const SolveScalars sc = a.sc[item * a.sc_stride];
+    double dl[E];
+    if constexpr (MODE != C2R_EXPORT) {
+#pragma unroll
+        for (int e = 0; e < E; ++e) dl[e] = dptr[(long long)(t + TP * e) * a.inner];
+    }
 
     // per-mode accumulators:
     //  apply:   acc = sum_m delta^m t_m (a1 = delta^m)
@@ -561,7 +567,7 @@ __global__ __launch_bounds__(W*(N / E)) void k_c2r0(C2RArgs<T> a) {
         if constexpr (MODE == C2R_APPLY) {
 #pragma unroll
             for (int e = 0; e < E; ++e) {
-                const double d = dptr[(long long)(t + TP * e) * a.inner];
+                const double d = dl[e];
                 acc[e] += a1[e] * (double(y[e].x) + d * double(y[e].y));
                 a1[e] *= d * d;
             }
@@ -570,7 +576,7 @@ __global__ __launch_bounds__(W*(N / E)) void k_c2r0(C2RArgs<T> a) {
             const double b0c = (tr == 0) ? sc.beta0 : 0.0;
 #pragma unroll
             for (int e = 0; e < E; ++e) {
-                const double d = dptr[(long long)(t + TP * e) * a.inner];
+                const double d = dl[e];
                 acc[e] += (k0c + a1[e]) * double(y[e].x) + (b0c + b1[e]) * double(y[e].y);
                 a1[e] *= d;
                 b1[e] *= d;
@@ -578,7 +584,7 @@ __global__ __launch_bounds__(W*(N / E)) void k_c2r0(C2RArgs<T> a) {
         } else if constexpr (MODE == C2R_KICK_GENERIC) {
 #pragma unroll
             for (int e = 0; e < E; ++e) {
-                const double d = dptr[(long long)(t + TP * e) * a.inner];
+                const double d = dl[e];
                 for (int h = 0; h < 2; ++h) {
                     const int sidx = 2 * tr + h;
                     if (sidx >= nS) break;

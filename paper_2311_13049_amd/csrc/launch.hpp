@@ -27,7 +27,9 @@ struct Launch {
     static int c2r_tile(int N, int variant);
     template <typename TI>
     static hipError_t contig(int N, const ContigArgs<T, TI>& a, int items, hipStream_t s);
-    static hipError_t mid(int N, int dir, const MidArgs<T>& a, int planes, int items, hipStream_t s);
+    static hipError_t mid(int N, int dir, const MidArgs<T>& a, int planes, int items, hipStream_t s,
+                          int variant = 0);
+    static int mid_tile(int N, int variant);
     // forward axis-0 transform of real T data into FP64 half spectra
     static hipError_t r2c0(int N, const R2CArgs<T>& a, int items, hipStream_t s);
     static int r2c0_w(int N);

@@ -77,21 +77,45 @@ hipError_t Launch<T>::contig(int N, const ContigArgs<T, TI>& a, int items, hipSt
     }
 }
 
+// variants: 0 -> W = tile_width columns; 1 -> 2W columns when the FFT
+// buffer stays within 66 KB of LDS
 template <typename T>
 hipError_t Launch<T>::mid(int N, int dir, const MidArgs<T>& a, int planes, int items,
-                          hipStream_t s) {
+                          hipStream_t s, int variant) {
     switch (N) {
 #define C_(n)                                                                           \
     case n: {                                                                           \
         constexpr int E = e_mid(n), W = tile_width<T, n>();                             \
-        dim3 grid(planes * a.tiles_per_plane, items * a.nf);                            \
-        if (dir < 0) k_mid<T, n, E, W, -1><<<grid, dim3(W * (n / E)), 0, s>>>(a);       \
-        else k_mid<T, n, E, W, +1><<<grid, dim3(W * (n / E)), 0, s>>>(a);              \
+        constexpr int W2 = (2 * W * n * int(sizeof(cpx<T>)) <= 67584) ? 2 * W : W;      \
+        const int w = (variant == 1) ? W2 : W;                                          \
+        dim3 grid(planes * ((a.n2 + w - 1) / w), items * a.nf);                         \
+        if (variant == 1 && W2 != W) {                                                  \
+            if (dir < 0) k_mid<T, n, E, W2, -1><<<grid, dim3(W2 * (n / E)), 0, s>>>(a); \
+            else k_mid<T, n, E, W2, +1><<<grid, dim3(W2 * (n / E)), 0, s>>>(a);        \
+        } else {                                                                        \
+            if (dir < 0) k_mid<T, n, E, W, -1><<<grid, dim3(W * (n / E)), 0, s>>>(a);   \
+            else k_mid<T, n, E, W, +1><<<grid, dim3(W * (n / E)), 0, s>>>(a);          \
+        }                                                                               \
         return hipGetLastError();                                                       \
     }
         VOFL_MULTI_SIZES(C_)
 #undef C_
         default: return hipErrorInvalidValue;
+    }
+}
+
+template <typename T>
+int Launch<T>::mid_tile(int N, int variant) {
+    switch (N) {
+#define C_(n)                                                                           \
+    case n: {                                                                           \
+        constexpr int W = tile_width<T, n>();                                           \
+        constexpr int W2 = (2 * W * n * int(sizeof(cpx<T>)) <= 67584) ? 2 * W : W;      \
+        return variant == 1 ? W2 : W;                                                   \
+    }
+        VOFL_MULTI_SIZES(C_)
+#undef C_
+        default: return 0;
     }
 }
 

@@ -193,7 +193,8 @@ struct vofl_plan_s {
     void* work = nullptr;
     int* flag = nullptr;
     std::vector<void*> allocs;
-    int c2r_variant = 0;               // k_c2r0 elements-per-thread variant
+    int c2r_variant = 0;               // k_c2r0 tile variant
+    int mid_variant = 1;               // k_mid tile variant (1: double-width tiles)
     hipStream_t own_stream = nullptr;  // used by vofl_step_batch
     hipEvent_t fork_ev = nullptr, join_ev = nullptr;
     // timing
@@ -369,10 +370,10 @@ hipError_t mid(vofl_plan_s* p, const char* name, int dir, cpx<T>* buf, long long
     m.nf = nf;
     m.H = g.H;
     m.n2 = g.n[2];
-    const int W = Launch<T>::tile_w(g.n[1]);
+    const int W = Launch<T>::mid_tile(g.n[1], p->mid_variant);
     m.tiles_per_plane = (g.n[2] + W - 1) / W;
     m.tw = tw;
-    return p->timed(name, s, [&] { return Launch<T>::mid(g.n[1], dir, m, g.n0h, items, s); });
+    return p->timed(name, s, [&] { return Launch<T>::mid(g.n[1], dir, m, g.n0h, items, s, p->mid_variant); });
 }
 
 // forward transform of real fields (items of Nreal values) into the FP64
@@ -662,6 +663,7 @@ int vofl_plan(const vofl_desc* d, void* stream, vofl_plan_t* out) {
     }
     p->sc_host = sc;
     if (const char* ev = std::getenv("VOFL_C2R_VARIANT")) p->c2r_variant = std::atoi(ev);
+    if (const char* ev = std::getenv("VOFL_MID_VARIANT")) p->mid_variant = std::atoi(ev);
     rc = (d->precision == VOFL_FP32) ? upload_tables<float>(p, delta, A, B)
                                      : upload_tables<double>(p, delta, A, B);
     if (rc) {
