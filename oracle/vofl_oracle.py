@@ -69,8 +69,32 @@ __all__ = [
     "fft_bins", "wavenumbers", "mu_squared", "gamma_from_Q",
     "seismic_coefficients", "dense_dft", "dense_apply", "dense_matrix_1d",
     "mterm_apply", "seismic_op_order", "tsfp2_generic", "damped_propagator",
-    "tsfp2_seismic", "weighted_l2", "rel_l2",
+    "tsfp2_seismic", "weighted_l2", "rel_l2", "mterm_apply_at", "set_fft_workers",
 ]
+
+# FFT backend: numpy's pocketfft by default; set_fft_workers(n) switches to
+# scipy.fft with n threads (same transform, a library primitive either way).
+_FFT_WORKERS = 0
+
+
+def set_fft_workers(n: int) -> None:
+    """Use scipy.fft with n worker threads for the oracle's FFTs (0: numpy)."""
+    global _FFT_WORKERS
+    _FFT_WORKERS = int(n)
+
+
+def _fftn(x):
+    if _FFT_WORKERS:
+        import scipy.fft
+        return scipy.fft.fftn(x, workers=_FFT_WORKERS)
+    return np.fft.fftn(x)
+
+
+def _ifftn(x):
+    if _FFT_WORKERS:
+        import scipy.fft
+        return scipy.fft.ifftn(x, workers=_FFT_WORKERS)
+    return np.fft.ifftn(x)
 
 
 # ---------------------------------------------------------------------------
@@ -234,7 +258,7 @@ def mterm_apply(u, s, lo, hi, M: int) -> np.ndarray:
     N = u.size
     s0 = float(np.mean(s))
     delta = s - s0
-    uhat = np.fft.fftn(u) / N
+    uhat = _fftn(u) / N
     mu2 = mu_squared(u.shape, lo, hi)
     nz = mu2 > 0.0
     lnmu2 = np.zeros_like(mu2)
@@ -244,9 +268,47 @@ def mterm_apply(u, s, lo, hi, M: int) -> np.ndarray:
     out = np.zeros(u.shape)
     for m in range(M + 1):
         coef = lnmu2 ** m / math.factorial(m) * base        # zero at k = 0
-        inner = np.real(np.fft.ifftn(coef * uhat)) * N       # sum over k
+        inner = np.real(_ifftn(coef * uhat)) * N             # sum over k
         out += delta ** m * inner
     return out
+
+
+def mterm_apply_at(u, s, lo, hi, M: int, points) -> np.ndarray:
+    """(2.13) at selected grid points, each computed on its own.
+
+    For a point x_j: sum_m delta_j^m sum_{k != 0} l_m(k) |mu_k|^{2 s0} u_hat_k
+    exp(i mu_k.(x_j - a)), the inner sum taken over all k explicitly. points
+    is a sequence of index tuples.
+    """
+    u = np.asarray(u, dtype=np.float64)
+    s = np.broadcast_to(np.asarray(s, dtype=np.float64), u.shape)
+    shape = u.shape
+    N = u.size
+    s0 = float(np.mean(s))
+    uhat = _fftn(u) / N
+    mu2 = mu_squared(shape, lo, hi)
+    nz = mu2 > 0.0
+    lnmu2 = np.zeros_like(mu2)
+    lnmu2[nz] = np.log(mu2[nz])
+    base = np.zeros_like(mu2)
+    base[nz] = mu2[nz] ** s0
+    out = []
+    for j in points:
+        ph = np.ones(shape, dtype=np.complex128)
+        for ax, n in enumerate(shape):
+            k = fft_bins(n)
+            e = np.exp(2j * np.pi * np.mod(k * j[ax], n) / n)
+            sh = [1] * len(shape)
+            sh[ax] = n
+            ph = ph * e.reshape(sh)
+        w = base * uhat * ph
+        d = s[tuple(j)] - s0
+        val = 0.0
+        for m in range(M + 1):
+            inner = np.real(np.sum(lnmu2 ** m / math.factorial(m) * w))
+            val += d ** m * inner
+        out.append(val)
+    return np.array(out)
 
 
 # ---------------------------------------------------------------------------
@@ -254,11 +316,11 @@ def mterm_apply(u, s, lo, hi, M: int) -> np.ndarray:
 # ---------------------------------------------------------------------------
 
 def _to_spec(u):
-    return np.fft.fftn(u) / u.size
+    return _fftn(u) / u.size
 
 
 def _to_phys(uhat):
-    return np.real(np.fft.ifftn(uhat)) * uhat.size
+    return np.real(_ifftn(uhat)) * uhat.size
 
 
 def tsfp2_generic(phi, psi, s, kappa: float, lo, hi, M: int, dt: float,

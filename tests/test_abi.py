@@ -1,0 +1,107 @@
+"""Host-side checks of libvofl: it loads, exports every function declared in
+include/vofl.h, and validates descriptors on the host (no GPU compute)."""
+
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_2311_13049_amd import vofl as V
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "vofl.h")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(vofl_[a-z_]+)\s*\(", text)))
+
+
+def test_library_exports_every_declared_function():
+    lib = V.load_library()
+    names = declared_functions()
+    assert len(names) >= 10
+    for n in names:
+        assert hasattr(lib, n), n
+    assert set(names) == set(V.ABI_FUNCTIONS)
+
+
+def test_version_string():
+    assert "gfx950" in V.vofl_version()
+
+
+def _desc(**kw):
+    base = dict(shape=(16, 32), lo=(-1.0, -2.0), hi=(1.0, 2.0), gamma=np.full(512, 0.1), M=4, dt=1e-3)
+    base.update(kw)
+    shape, lo, hi = base.pop("shape"), base.pop("lo"), base.pop("hi")
+    return V.make_desc(shape, lo, hi, **base)
+
+
+def _rc(**kw):
+    d, keep = _desc(**kw)
+    try:
+        V.vofl_plan_footprint(d)
+        return 0
+    except V.VoflError as e:
+        return e.code
+
+
+@pytest.mark.parametrize("kw,code", [
+    (dict(shape=(15, 32), gamma=np.full(480, 0.1)), V.VOFL_ERR_INVALID),            # odd n
+    (dict(shape=(0, 32), gamma=np.zeros(0)), V.VOFL_ERR_INVALID),
+    (dict(shape=(24, 32), gamma=np.full(768, 0.1)), V.VOFL_ERR_UNSUPPORTED),         # no length-24 transform
+    (dict(gamma=np.full(512, 0.5)), V.VOFL_ERR_INVALID),                             # gamma >= 1/2
+    (dict(gamma=np.full(512, -0.01)), V.VOFL_ERR_INVALID),
+    (dict(gamma=None, Q=np.zeros(512)), V.VOFL_ERR_INVALID),                         # Q <= 0
+    (dict(gamma=None, Q=np.full(512, np.nan)), V.VOFL_ERR_INVALID),
+    (dict(Q=np.full(512, 10.0)), V.VOFL_ERR_INVALID),                                # both Q and gamma
+    (dict(gamma=None), V.VOFL_ERR_INVALID),                                          # neither
+    (dict(M=-1), V.VOFL_ERR_INVALID),
+    (dict(M=65), V.VOFL_ERR_INVALID),
+    (dict(dt=0.0), V.VOFL_ERR_INVALID),
+    (dict(dt=float("inf")), V.VOFL_ERR_INVALID),
+    (dict(c0=0.0), V.VOFL_ERR_INVALID),
+    (dict(omega0=-1.0), V.VOFL_ERR_INVALID),
+    (dict(lo=(1.0, 0.0), hi=(1.0, 1.0)), V.VOFL_ERR_INVALID),                        # empty box
+    (dict(hbm_budget=1024), V.VOFL_ERR_NOMEM),
+    (dict(model="generic", gamma=None, s=np.full(512, 2.0), kappa=1.0), V.VOFL_ERR_INVALID),
+    (dict(model="generic", gamma=None, s=np.full(512, 1.0), kappa=0.0), V.VOFL_ERR_INVALID),
+    (dict(model="generic", gamma=None, s=None, kappa=1.0), V.VOFL_ERR_INVALID),
+    (dict(batch=-2), V.VOFL_ERR_INVALID),
+])
+def test_descriptor_validation(kw, code):
+    assert _rc(**kw) == code
+
+
+def test_valid_descriptors_and_footprint_formula():
+    assert _rc() == 0
+    assert _rc(gamma=None, Q=np.full(512, np.inf)) == 0          # Q = +inf gives gamma = 0
+    assert _rc(model="generic", gamma=None, s=np.full(512, 1.3), kappa=1.0) == 0
+    n0, n1, M = 16, 32, 4
+    d, keep = _desc(precision="fp32", max_batch=3)
+    b = V.vofl_plan_footprint(d)
+    H = (n0 // 2 + 1) * n1
+    slots = max(2 * (M + 1) + 3, 3 * (M + 1))
+    expect = (n0 + n1) * (8 + 16 + 8) + 512 * (8 + 8) + 64 + 256 + slots * H * 8 + max(2, 3) * H * 16
+    assert b == expect
+
+
+def test_null_plan_arguments_are_rejected():
+    lib = V.load_library()
+    assert lib.vofl_apply(None, 1, None, None, 1, None) == V.VOFL_ERR_INVALID
+    assert lib.vofl_step(None, None, None, 1, None) == V.VOFL_ERR_INVALID
+    assert lib.vofl_destroy(None) == V.VOFL_ERR_INVALID
+    assert "NULL" in V.vofl_last_error()
+
+
+def test_plan_without_device_reports_device_error():
+    """On a host without a GPU the plan fails cleanly with VOFL_ERR_DEVICE."""
+    d, keep = _desc()
+    try:
+        h = V.vofl_plan(d)
+    except V.VoflError as e:
+        assert e.code == V.VOFL_ERR_DEVICE
+        return
+    V.vofl_destroy(h)  # a GPU is present: the plan is valid

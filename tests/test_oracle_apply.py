@@ -9,7 +9,7 @@ import math
 import numpy as np
 import pytest
 
-from oracle import (dense_apply, dense_dft, dense_matrix_1d, mterm_apply,
+from oracle import (dense_apply, dense_dft, dense_matrix_1d, mterm_apply, mterm_apply_at,
                     rel_l2, seismic_op_order)
 from workloads import c1_inputs, grid_1d, mesh, paper_s1
 
@@ -164,3 +164,26 @@ def test_reflection_symmetry_of_operator():
     out = mterm_apply(u, s, lo, hi, 12)
     # x_j -> -x_j maps index j to (n - j) mod n on this grid
     np.testing.assert_allclose(out, out[(-np.arange(n)) % n], atol=1e-12 * np.abs(out).max())
+
+
+def test_pointwise_evaluation_matches_full_field_and_single_mode():
+    """mterm_apply_at (used to sample huge grids) agrees with mterm_apply and,
+    on one mode, with the truncated exponential series at those points."""
+    shape, lo, hi = (8, 12, 10), (-1.0, -2.0, -1.5), (1.0, 2.0, 1.5)
+    rng = np.random.default_rng(5)
+    u = rng.standard_normal(shape)
+    s = 1.0 + 0.2 * rng.random(shape)
+    full = mterm_apply(u, s, lo, hi, 7)
+    pts = [(0, 0, 0), (3, 5, 7), (7, 11, 9)]
+    got = mterm_apply_at(u, s, lo, hi, 7, pts)
+    np.testing.assert_allclose(got, [full[p] for p in pts], atol=1e-12 * np.abs(full).max())
+    X = mesh(shape, lo, hi)
+    mu = (2 * np.pi * 2 / 2.0, 2 * np.pi * 3 / 4.0, 0.0)
+    mode = np.cos(mu[0] * (X[0] - lo[0]) + mu[1] * (X[1] - lo[1]))
+    vals = mterm_apply_at(mode, s, lo, hi, 3, pts)
+    s0 = s.mean()
+    m2 = mu[0] ** 2 + mu[1] ** 2
+    for v, p in zip(vals, pts):
+        z = (s[p] - s0) * np.log(m2)
+        series = sum(z ** m / math.factorial(m) for m in range(4))
+        assert abs(v - m2 ** s0 * series * mode[p]) <= 1e-12 * m2 ** 2
