@@ -43,6 +43,26 @@ __device__ __forceinline__ cpx<T> twmul(cpx<T> a, cpx<T> w) {
     return cmul(a, w);
 }
 
+// Raw buffer load of one complex value: the descriptor (base, byte size)
+// lives in scalar registers, the lane supplies a 32-bit byte offset; the
+// hardware returns zero for offsets past the size. The third descriptor word
+// is the gfx9 raw-buffer format (no swizzle, 32-bit data).
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t make_rsrc(const void* base, unsigned bytes) {
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), (short)0, (int)bytes, 0x00020000);
+}
+template <typename T>
+__device__ __forceinline__ cpx<T> buffer_load_cpx(__amdgpu_buffer_rsrc_t r, unsigned off) {
+    cpx<T> c;
+    if constexpr (sizeof(T) == 4) {
+        auto v = __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, 0);
+        __builtin_memcpy(&c, &v, 8);
+    } else {
+        auto v = __builtin_amdgcn_raw_buffer_load_b128(r, off, 0, 0);
+        __builtin_memcpy(&c, &v, 16);
+    }
+    return c;
+}
+
 // ---------------------------------------------------------------------------
 // small DFTs in registers
 // ---------------------------------------------------------------------------
@@ -174,14 +194,16 @@ constexpr int num_stages(int N, int E) {
     return s;
 }
 
-// LDS views. Pencil-major: element i of a pencil at base[i + i/16]
-// (one pad slot per 16 elements). Column-interleaved: element i of column c
-// at base[i*W + c] (columns of a tile side by side).
+// LDS views. Pencil-major: element i of a pencil at base[i + i/8] (one pad
+// slot per 8 elements: the radix-8 Stockham writes at stride 8, 64 and the
+// unit-stride reads then fall on distinct banks for 32 lanes).
+// Column-interleaved: element i of column c at base[i*W + c] (columns of a
+// tile side by side; consecutive lanes hit consecutive addresses).
 template <typename T>
 struct LdsPencil {
     cpx<T>* base;
-    __device__ __forceinline__ cpx<T>& operator[](int i) const { return base[i + (i >> 4)]; }
-    static constexpr int footprint(int N) { return N + N / 16; }
+    __device__ __forceinline__ cpx<T>& operator[](int i) const { return base[i + (i >> 3)]; }
+    static constexpr int footprint(int N) { return N + N / 8; }
 };
 template <typename T, int W>
 struct LdsColumn {

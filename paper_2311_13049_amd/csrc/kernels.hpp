@@ -473,8 +473,9 @@ __device__ __forceinline__ int c2r_nslots(int mode, int M) {
     }
 }
 
-template <typename T, int N, int E, int W, int MODE>
-__global__ __launch_bounds__(W*(N / E)) void k_c2r0(C2RArgs<T> a) {
+template <typename T, int N, int E, int W, int MODE, int WPE>
+__global__ __launch_bounds__(W*(N / E)) __attribute__((amdgpu_waves_per_eu(WPE)))
+void k_c2r0(C2RArgs<T> a) {
     static_assert(MODE >= 0 && MODE <= 3, "mode");
     constexpr int TP = N / E;
     __shared__ cpx<T> lds_fft[N * W];
@@ -487,7 +488,7 @@ __global__ __launch_bounds__(W*(N / E)) void k_c2r0(C2RArgs<T> a) {
     const int colc = active ? col : 0;
     const int item = blockIdx.y;
     const LdsColumn<T, W> lds{lds_fft + c};
-    const cpx<T>* ibase = a.in + (long long)item * a.istride + colc;
+    const cpx<T>* ibase = a.in + (long long)item * a.istride;  // uniform
     const int nT = c2r_transforms(MODE, a.M);
     const int nS = c2r_nslots(MODE, a.M);
 
@@ -495,17 +496,26 @@ __global__ __launch_bounds__(W*(N / E)) void k_c2r0(C2RArgs<T> a) {
     // min(k, N-k) of both slots of a pair directly into registers (the
     // mirror rows of two threads coincide and come from cache the second
     // time); the next pair is loaded while the current one is transformed.
+    // Per-lane 32-bit byte offsets (a half field is below 4 GiB, checked by
+    // the plan); the slot base is uniform.
+    unsigned roff[E];
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+        const int k = t + TP * e;
+        const int r = (k <= N / 2) ? k : N - k;
+        roff[e] = (unsigned(r) * unsigned(a.inner) + unsigned(colc)) * unsigned(sizeof(cpx<T>));
+    }
     cpx<T> p1[E], p2[E];
     auto load_pair = [&](int tr) __attribute__((always_inline)) {
         const int s1 = 2 * tr, s2 = 2 * tr + 1;
         const bool two = s2 < nS;
+        const unsigned bytes = unsigned(a.H * (long long)sizeof(cpx<T>));
+        const auto r1 = make_rsrc(ibase + (long long)s1 * a.H, bytes);
+        const auto r2 = make_rsrc(ibase + (long long)(two ? s2 : s1) * a.H, bytes);
 #pragma unroll
         for (int e = 0; e < E; ++e) {
-            const int k = t + TP * e;
-            const int r = (k <= N / 2) ? k : N - k;
-            const long long off = (long long)r * a.inner;
-            p1[e] = ibase[(long long)s1 * a.H + off];
-            p2[e] = two ? ibase[(long long)s2 * a.H + off] : cpx<T>{T(0), T(0)};
+            p1[e] = buffer_load_cpx<T>(r1, roff[e]);
+            p2[e] = two ? buffer_load_cpx<T>(r2, roff[e]) : cpx<T>{T(0), T(0)};
         }
     };
     // Y = a + i b with a, b the Hermitian extensions along axis 0
@@ -527,26 +537,29 @@ __global__ __launch_bounds__(W*(N / E)) void k_c2r0(C2RArgs<T> a) {
     };
 
     // delta at this thread's points, held in registers (FP64)
-    const double* dptr = a.delta + (long long)item * a.coef_stride + colc;
     const SolveScalars sc = a.sc[item * a.sc_stride];
     double dl[E];
     if constexpr (MODE != C2R_EXPORT) {
+        const double* dptr = a.delta + (long long)item * a.coef_stride + colc;
 #pragma unroll
         for (int e = 0; e < E; ++e) dl[e] = dptr[(long long)(t + TP * e) * a.inner];
     }
 
-    // per-mode accumulators:
-    //  apply:   acc = sum_m delta^m t_m (a1 = delta^m)
-    //  kick:    acc = (kappa0 - A) t1_0 + (beta0 - B) t2_0 + sum_{m>=1} delta^m (-A t1_m - B t2_m),
-    //           with a1 = -A delta^m, b1 = -B delta^m (FP64)
-    //  generic: acc = -kappa sum_{s=1..M} delta^s t_s (a1 = delta^s), b1 = IDFT(u_hat)
-    double acc[E], a1[E], b1[E];
+    // Accumulation in the plan precision T (FP32 or FP64); the powers
+    // delta^m and the coefficients (kappa0 - A), (beta0 - B), -A delta^m,
+    // -B delta^m are formed in FP64 and rounded once:
+    //  apply:   acc = sum_m delta^m t_m
+    //  kick:    acc = (kappa0 - A) t1_0 + (beta0 - B) t2_0 + sum_{m>=1} delta^m (-A t1_m - B t2_m)
+    //  generic: acc = -kappa sum_{s=1..M} delta^s t_s, uu = IDFT(u_hat)
+    T acc[E], cA[E], cB[E];
+    double dm[E];
     cpx<T> y[E];
 #pragma unroll
     for (int e = 0; e < E; ++e) {
-        acc[e] = 0.0;
-        a1[e] = 1.0;
-        b1[e] = 0.0;
+        acc[e] = T(0);
+        dm[e] = 1.0;
+        cA[e] = T(0);
+        cB[e] = T(0);
     }
     if constexpr (MODE == C2R_KICK) {
         const T* Ap = a.A + (long long)item * a.coef_stride + colc;
@@ -554,8 +567,8 @@ __global__ __launch_bounds__(W*(N / E)) void k_c2r0(C2RArgs<T> a) {
 #pragma unroll
         for (int e = 0; e < E; ++e) {
             const long long off = (long long)(t + TP * e) * a.inner;
-            a1[e] = -double(Ap[off]);
-            b1[e] = -double(Bp[off]);
+            cA[e] = -Ap[off];
+            cB[e] = -Bp[off];
         }
     }
 
@@ -568,8 +581,8 @@ __global__ __launch_bounds__(W*(N / E)) void k_c2r0(C2RArgs<T> a) {
 #pragma unroll
             for (int e = 0; e < E; ++e) {
                 const double d = dl[e];
-                acc[e] += a1[e] * (double(y[e].x) + d * double(y[e].y));
-                a1[e] *= d * d;
+                acc[e] += T(dm[e]) * y[e].x + T(dm[e] * d) * y[e].y;
+                dm[e] *= d * d;
             }
         } else if constexpr (MODE == C2R_KICK) {
             const double k0c = (tr == 0) ? sc.kappa0 : 0.0;
@@ -577,9 +590,10 @@ __global__ __launch_bounds__(W*(N / E)) void k_c2r0(C2RArgs<T> a) {
 #pragma unroll
             for (int e = 0; e < E; ++e) {
                 const double d = dl[e];
-                acc[e] += (k0c + a1[e]) * double(y[e].x) + (b0c + b1[e]) * double(y[e].y);
-                a1[e] *= d;
-                b1[e] *= d;
+                const T ca = T(k0c + double(cA[e]) * dm[e]);
+                const T cb = T(b0c + double(cB[e]) * dm[e]);
+                acc[e] += ca * y[e].x + cb * y[e].y;
+                dm[e] *= d;
             }
         } else if constexpr (MODE == C2R_KICK_GENERIC) {
 #pragma unroll
@@ -588,12 +602,12 @@ __global__ __launch_bounds__(W*(N / E)) void k_c2r0(C2RArgs<T> a) {
                 for (int h = 0; h < 2; ++h) {
                     const int sidx = 2 * tr + h;
                     if (sidx >= nS) break;
-                    const double val = h == 0 ? double(y[e].x) : double(y[e].y);
+                    const T val = h == 0 ? y[e].x : y[e].y;
                     if (sidx == a.M + 1) {
-                        b1[e] = val;
+                        cB[e] = val;  // u at the half step, for the cubic term
                     } else {
-                        if (sidx > 0) acc[e] -= sc.kappa0 * a1[e] * val;
-                        a1[e] *= d;
+                        if (sidx > 0) acc[e] -= T(sc.kappa0 * dm[e]) * val;
+                        dm[e] *= d;
                     }
                 }
             }
@@ -616,7 +630,7 @@ __global__ __launch_bounds__(W*(N / E)) void k_c2r0(C2RArgs<T> a) {
         if (active) {
             T* o = a.r0 + (long long)item * a.Nreal + colc;
 #pragma unroll
-            for (int e = 0; e < E; ++e) o[(long long)(t + TP * e) * a.inner] = T(acc[e]);
+            for (int e = 0; e < E; ++e) o[(long long)(t + TP * e) * a.inner] = acc[e];
         }
         return;
     }
@@ -625,10 +639,10 @@ __global__ __launch_bounds__(W*(N / E)) void k_c2r0(C2RArgs<T> a) {
     bool bad = false;
 #pragma unroll
     for (int e = 0; e < E; ++e) {
-        double dv = acc[e];
-        if constexpr (MODE == C2R_KICK_GENERIC) dv += sc.lambda * b1[e] * b1[e] * b1[e];
+        T dv = acc[e];
+        if constexpr (MODE == C2R_KICK_GENERIC) dv += T(sc.lambda) * cB[e] * cB[e] * cB[e];
         bad |= !isfinite(dv);
-        z[e] = {T(dv), T(0)};
+        z[e] = {dv, T(0)};
     }
     if (bad && active) a.flag[0] = 1;
     fft_pencil<T, N, E, -1>(z, t, lds, tw_s);

@@ -135,21 +135,23 @@ hipError_t Launch<T>::r2c0(int N, const R2CArgs<T>& a, int items, hipStream_t s)
     }
 }
 
-template <typename T, int n, int E, int W>
+template <typename T, int n, int E, int W, int WPE>
 hipError_t c2r0_mode(const C2RArgs<T>& a, int items, hipStream_t s) {
     const dim3 block(W * (n / E));
     const dim3 grid((a.inner + W - 1) / W, items);
     switch (a.mode) {
-        case C2R_APPLY: k_c2r0<T, n, E, W, C2R_APPLY><<<grid, block, 0, s>>>(a); break;
-        case C2R_KICK: k_c2r0<T, n, E, W, C2R_KICK><<<grid, block, 0, s>>>(a); break;
-        case C2R_EXPORT: k_c2r0<T, n, E, W, C2R_EXPORT><<<grid, block, 0, s>>>(a); break;
-        case C2R_KICK_GENERIC: k_c2r0<T, n, E, W, C2R_KICK_GENERIC><<<grid, block, 0, s>>>(a); break;
+        case C2R_APPLY: k_c2r0<T, n, E, W, C2R_APPLY, WPE><<<grid, block, 0, s>>>(a); break;
+        case C2R_KICK: k_c2r0<T, n, E, W, C2R_KICK, WPE><<<grid, block, 0, s>>>(a); break;
+        case C2R_EXPORT: k_c2r0<T, n, E, W, C2R_EXPORT, WPE><<<grid, block, 0, s>>>(a); break;
+        case C2R_KICK_GENERIC: k_c2r0<T, n, E, W, C2R_KICK_GENERIC, WPE><<<grid, block, 0, s>>>(a); break;
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
 }
 
-// variants: 0 -> (W, 8), 1 -> (W, 16), 2 -> (W/2, 8) with W = c2r_width
+// variants: 0 -> (W, 8); 1 -> (W, 16); 2 -> (W/2, 8); 3 -> (W, 8) held to
+// 4 waves per SIMD (two workgroups per CU, registers spill); 4 -> (W/2, 16);
+// W = c2r_width
 template <typename T>
 hipError_t Launch<T>::c2r0(int N, const C2RArgs<T>& a, int items, hipStream_t s, int variant) {
     switch (N) {
@@ -158,9 +160,11 @@ hipError_t Launch<T>::c2r0(int N, const C2RArgs<T>& a, int items, hipStream_t s,
         constexpr int W = c2r_width<T, n>(), E = e_c2r0(n);                             \
         constexpr int E2 = (n >= 16) ? 16 : E;                                          \
         constexpr int W2 = (W >= 8) ? W / 2 : W;                                        \
-        if (variant == 1 && E2 != E) return c2r0_mode<T, n, E2, W>(a, items, s);        \
-        if (variant == 2 && W2 != W) return c2r0_mode<T, n, E, W2>(a, items, s);        \
-        return c2r0_mode<T, n, E, W>(a, items, s);                                      \
+        if (variant == 1 && E2 != E) return c2r0_mode<T, n, E2, W, 1>(a, items, s);     \
+        if (variant == 2 && W2 != W) return c2r0_mode<T, n, E, W2, 1>(a, items, s);     \
+        if (variant == 3 && W * (n / E) <= 512) return c2r0_mode<T, n, E, W, 4>(a, items, s); \
+        if (variant == 4 && E2 != E && W2 != W) return c2r0_mode<T, n, E2, W2, 1>(a, items, s); \
+        return c2r0_mode<T, n, E, W, 1>(a, items, s);                                   \
     }
         VOFL_MULTI_SIZES(C_)
 #undef C_

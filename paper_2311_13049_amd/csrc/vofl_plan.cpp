@@ -140,6 +140,8 @@ int derive(const vofl_desc* d, Geometry& g) {
         g.inner = (int)(g.Nreal / g.n[0]);
         g.H = (long long)g.n0h * g.inner;
         g.npencils = (int)(g.H / g.nlast);
+        if ((unsigned long long)g.H * 16ULL >= (1ULL << 32))
+            return fail(VOFL_ERR_UNSUPPORTED, "half spectrum of %lld elements exceeds 32-bit byte offsets", g.H);
         g.nterm = (d->model == VOFL_MODEL_SEISMIC) ? 2 * (d->M + 1) : d->M + 2;
         g.step_slots = g.nterm + 3;   // terms, dv, export pair
         g.apply_slots = d->M + 1;     // terms
