@@ -212,8 +212,23 @@ struct LdsColumn {
     static constexpr int footprint(int N) { return N * W; }
 };
 
+// Synchronisation between the LDS write and read of an exchange. A
+// transform whose threads all sit in one wavefront only needs its own LDS
+// operations completed and ordered (no workgroup barrier); otherwise the
+// whole workgroup synchronises.
+template <bool WAVE>
+__device__ __forceinline__ void exchange_sync() {
+    if constexpr (WAVE) {
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    } else {
+        __syncthreads();
+    }
+}
+
 // One Stockham stage with stride NS (product of the radices done before).
-template <typename T, int N, int E, int DIR, int NS, class Lds>
+template <typename T, int N, int E, int DIR, int NS, class Lds, bool WAVE = false>
 __device__ __forceinline__ void fft_stages(cpx<T> (&v)[E], const int t, const Lds& lds,
                                            const cpx<T>* __restrict__ tw) {
     constexpr int R = pick_radix(N / NS, E);
@@ -248,22 +263,25 @@ __device__ __forceinline__ void fft_stages(cpx<T> (&v)[E], const int t, const Ld
 #pragma unroll
         for (int e = 0; e < E; ++e) v[e] = out[e];
     } else {
-        __syncthreads();
+        exchange_sync<WAVE>();
 #pragma unroll
         for (int e = 0; e < E; ++e) v[e] = lds[t + e * TP];
-        __syncthreads();
-        fft_stages<T, N, E, DIR, NS * R>(v, t, lds, tw);
+        exchange_sync<WAVE>();
+        fft_stages<T, N, E, DIR, NS * R, Lds, WAVE>(v, t, lds, tw);
     }
 }
 
 // Full length-N transform of the pencil held as v[e] = x[t + TP*e].
-// Every thread of the workgroup must call this (it contains barriers).
-template <typename T, int N, int E, int DIR, class Lds>
+// With WAVE = false every thread of the workgroup must call this (it
+// contains workgroup barriers); with WAVE = true the pencil's TP threads
+// must lie in one wavefront and only they synchronise.
+template <typename T, int N, int E, int DIR, class Lds, bool WAVE = false>
 __device__ __forceinline__ void fft_pencil(cpx<T> (&v)[E], const int t, const Lds& lds,
                                            const cpx<T>* __restrict__ tw) {
     static_assert(N % E == 0, "E must divide N");
     static_assert(num_stages(N, E) > 0, "length not supported");
-    fft_stages<T, N, E, DIR, 1>(v, t, lds, tw);
+    static_assert(!WAVE || (N / E) <= 64, "a wave-synchronised pencil must fit in one wavefront");
+    fft_stages<T, N, E, DIR, 1, Lds, WAVE>(v, t, lds, tw);
 }
 
 }  // namespace vofl

@@ -168,6 +168,9 @@ __global__ __launch_bounds__(P*(N / E)) void k_contig(ContigArgs<T, TI> a) {
     const double m2base = a.mu2_0[k0] + (a.mu2_1 ? a.mu2_1[k1] : 0.0);
     const long long pen = (long long)pc * N;
     const SolveScalars sc = a.sc[bi * a.sc_stride];
+    // a pencil's TP threads are consecutive and TP divides 64: every
+    // transform stays inside one wavefront
+    constexpr bool WV = (TP <= 64) && (64 % TP == 0);
 
     cpx<double> uh[E], vh[E];
     if (a.in_kind == IN_KICK) {
@@ -175,7 +178,7 @@ __global__ __launch_bounds__(P*(N / E)) void k_contig(ContigArgs<T, TI> a) {
         const cpx<TI>* src = a.in + (long long)bi * a.in_istride + pen;
 #pragma unroll
         for (int e = 0; e < E; ++e) d[e] = src[t + TP * e];
-        fft_pencil<TI, N, E, -1>(d, t, ldsi, twi_s);
+        fft_pencil<TI, N, E, -1, LdsPencil<TI>, WV>(d, t, ldsi, twi_s);
         const cpx<double>* Us = a.U + (long long)bi * a.H + pen;
         const cpx<double>* Vs = a.V + (long long)bi * a.H + pen;
         const double s = a.dt * a.invN;
@@ -191,7 +194,7 @@ __global__ __launch_bounds__(P*(N / E)) void k_contig(ContigArgs<T, TI> a) {
             const cpx<TI>* src = a.in + (long long)bi * a.in_istride + (long long)f * a.in_fstride + pen;
 #pragma unroll
             for (int e = 0; e < E; ++e) d[e] = src[t + TP * e];
-            fft_pencil<TI, N, E, -1>(d, t, ldsi, twi_s);
+            fft_pencil<TI, N, E, -1, LdsPencil<TI>, WV>(d, t, ldsi, twi_s);
 #pragma unroll
             for (int e = 0; e < E; ++e) {
                 const cpx<double> z = {double(d[e].x) * a.invN, double(d[e].y) * a.invN};
@@ -251,7 +254,7 @@ __global__ __launch_bounds__(P*(N / E)) void k_contig(ContigArgs<T, TI> a) {
             cpx<T> x[E];
 #pragma unroll
             for (int e = 0; e < E; ++e) x[e] = from_d<T>(vh[e]);
-            fft_pencil<T, N, E, +1>(x, t, lds, tw_s);
+            fft_pencil<T, N, E, +1, LdsPencil<T>, WV>(x, t, lds, tw_s);
             if (active) {
                 cpx<T>* d = dst0 + (long long)(a.M + 1) * a.H;
 #pragma unroll
@@ -265,7 +268,7 @@ __global__ __launch_bounds__(P*(N / E)) void k_contig(ContigArgs<T, TI> a) {
             cpx<T> x[E];
 #pragma unroll
             for (int e = 0; e < E; ++e) x[e] = from_d<T>(uh[e]);
-            fft_pencil<T, N, E, +1>(x, t, lds, tw_s);
+            fft_pencil<T, N, E, +1, LdsPencil<T>, WV>(x, t, lds, tw_s);
             if (active) {
                 cpx<T>* d = dst0 + (long long)m * a.H;
 #pragma unroll
@@ -283,7 +286,7 @@ __global__ __launch_bounds__(P*(N / E)) void k_contig(ContigArgs<T, TI> a) {
             cpx<T> x[E];
 #pragma unroll
             for (int e = 0; e < E; ++e) x[e] = from_d<T>(uh[e]);
-            fft_pencil<T, N, E, +1>(x, t, lds, tw_s);
+            fft_pencil<T, N, E, +1, LdsPencil<T>, WV>(x, t, lds, tw_s);
             if (active) {
                 cpx<T>* d = dst0 + (long long)(2 * m) * a.H;
 #pragma unroll
@@ -291,7 +294,7 @@ __global__ __launch_bounds__(P*(N / E)) void k_contig(ContigArgs<T, TI> a) {
             }
 #pragma unroll
             for (int e = 0; e < E; ++e) x[e] = from_d<T>(vh[e]);
-            fft_pencil<T, N, E, +1>(x, t, lds, tw_s);
+            fft_pencil<T, N, E, +1, LdsPencil<T>, WV>(x, t, lds, tw_s);
             if (active) {
                 cpx<T>* d = dst0 + (long long)(2 * m + 1) * a.H;
 #pragma unroll
@@ -310,7 +313,7 @@ __global__ __launch_bounds__(P*(N / E)) void k_contig(ContigArgs<T, TI> a) {
             cpx<T> x[E];
 #pragma unroll
             for (int e = 0; e < E; ++e) x[e] = from_d<T>(f == 0 ? uh[e] : vh[e]);
-            fft_pencil<T, N, E, +1>(x, t, lds, tw_s);
+            fft_pencil<T, N, E, +1, LdsPencil<T>, WV>(x, t, lds, tw_s);
             if (active) {
                 cpx<T>* d = dst0 + (long long)f * a.H;
 #pragma unroll
@@ -657,6 +660,202 @@ void k_c2r0(C2RArgs<T> a) {
                 dst[(long long)k * a.inner] = w;
             }
         }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// k_c2r0w: axis-0 kernel with wave-local transforms (apply, kick, generic)
+// ---------------------------------------------------------------------------
+// The workgroup stages the stored half rows (n0/2+1 rows of W columns) of a
+// slot pair into LDS with coalesced loads (each stored row read once), then
+// every wavefront transforms WV = 64/TP whole columns: its 16-element-per-
+// thread radix-16 FFT exchanges data only inside the wavefront, so the
+// transform needs no workgroup barrier. The next pair is loaded into
+// registers while the current one is transformed. Outputs are staged
+// through LDS and written with coalesced stores.
+template <typename T, int N, int E_, int NW_>
+struct C2RW {
+    static constexpr int E = E_;              // elements per thread
+    static constexpr int TP = N / E;          // threads per column
+    static constexpr int WV = 64 / TP;        // columns per wavefront
+    static constexpr int NW = NW_;            // wavefronts per workgroup
+    static constexpr int W = WV * NW;         // columns per workgroup
+    static constexpr int HR = N / 2 + 1;      // stored rows
+    static constexpr int NT = 64 * NW;
+    static constexpr int ST = (HR * W + NT - 1) / NT;  // staged elements per thread per slot
+    static constexpr int FPW = N + N / 8 + 16;         // one column's exchange region (padded)
+    static constexpr bool ok = (N % E == 0) && (TP <= 64) && (64 % TP == 0) && (TP >= 4);
+};
+
+template <typename T, int N, int E_, int NW_, int MODE>
+__global__ __launch_bounds__(64 * NW_) void k_c2r0w(C2RArgs<T> a) {
+    using G = C2RW<T, N, E_, NW_>;
+    static_assert(G::ok, "shape not supported by the wave-local axis-0 kernel");
+    static_assert(MODE == C2R_APPLY || MODE == C2R_KICK || MODE == C2R_KICK_GENERIC, "mode");
+    constexpr int E = G::E, TP = G::TP, WV = G::WV, W = G::W, HR = G::HR, NT = G::NT, ST = G::ST;
+    __shared__ cpx<T> stg[2 * HR * W];             // two staged half slots
+    __shared__ cpx<T> xch[G::NW * WV * G::FPW];     // per-column FFT exchange
+    __shared__ cpx<T> tw_s[N];
+    stage_twiddles<T, N>(tw_s, a.tw);
+    const int wv = threadIdx.x / 64, l = threadIdx.x % 64;
+    const int cw = l % WV, t = l / WV;
+    const int c = wv * WV + cw;                     // column within the tile
+    const int col0 = blockIdx.x * W;
+    const int col = col0 + c;
+    const bool active = col < a.inner;
+    const int colc = active ? col : 0;
+    const int item = blockIdx.y;
+    const LdsPencil<T> lds{xch + (wv * WV + cw) * G::FPW};
+    const cpx<T>* ibase = a.in + (long long)item * a.istride;
+    const int nT = c2r_transforms(MODE, a.M);
+    const int nS = c2r_nslots(MODE, a.M);
+    const unsigned bytes = unsigned(a.H * (long long)sizeof(cpx<T>));
+
+    // staged element j of this thread: i = threadIdx.x + j*NT -> (row, column)
+    unsigned soff[ST];
+#pragma unroll
+    for (int j = 0; j < ST; ++j) {
+        const int i = threadIdx.x + j * NT;
+        const int row = (i < HR * W) ? i / W : 0;
+        const int cg = col0 + i % W;
+        soff[j] = (unsigned(row) * unsigned(a.inner) + unsigned(cg < a.inner ? cg : 0)) *
+                  unsigned(sizeof(cpx<T>));
+    }
+    cpx<T> pf1[ST], pf2[ST];
+    auto load_pair = [&](int tr) __attribute__((always_inline)) {
+        const int s1 = 2 * tr, s2 = 2 * tr + 1;
+        const bool two = s2 < nS;
+        const auto r1 = make_rsrc(ibase + (long long)s1 * a.H, bytes);
+        const auto r2 = make_rsrc(ibase + (long long)(two ? s2 : s1) * a.H, bytes);
+#pragma unroll
+        for (int j = 0; j < ST; ++j) {
+            pf1[j] = buffer_load_cpx<T>(r1, soff[j]);
+            pf2[j] = two ? buffer_load_cpx<T>(r2, soff[j]) : cpx<T>{T(0), T(0)};
+        }
+    };
+    auto commit = [&]() __attribute__((always_inline)) {
+#pragma unroll
+        for (int j = 0; j < ST; ++j) {
+            const int i = threadIdx.x + j * NT;
+            if (i < HR * W) {
+                stg[i] = pf1[j];
+                stg[HR * W + i] = pf2[j];
+            }
+        }
+    };
+
+    const SolveScalars sc = a.sc[item * a.sc_stride];
+    double dl[E];
+    {
+        const double* dptr = a.delta + (long long)item * a.coef_stride + colc;
+#pragma unroll
+        for (int e = 0; e < E; ++e) dl[e] = dptr[(long long)(t + TP * e) * a.inner];
+    }
+    // accumulation in T; delta^m and the coefficients in FP64 (see k_c2r0)
+    T acc[E], cA[E], cB[E];
+    double dm[E];
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+        acc[e] = T(0);
+        dm[e] = 1.0;
+        cA[e] = T(0);
+        cB[e] = T(0);
+    }
+    if constexpr (MODE == C2R_KICK) {
+        const T* Ap = a.A + (long long)item * a.coef_stride + colc;
+        const T* Bp = a.B + (long long)item * a.coef_stride + colc;
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+            const long long off = (long long)(t + TP * e) * a.inner;
+            cA[e] = -Ap[off];
+            cB[e] = -Bp[off];
+        }
+    }
+
+    cpx<T> y[E];
+    load_pair(0);
+    for (int tr = 0; tr < nT; ++tr) {
+        commit();
+        __syncthreads();  // staged pair visible to every wavefront
+        const bool two = (2 * tr + 1) < nS;
+#pragma unroll
+        for (int e = 0; e < E; ++e) y[e] = hermitian_pair<T, N, W>(stg, two ? stg + HR * W : nullptr, c, t + TP * e);
+        __syncthreads();  // staging free for the next pair
+        if (tr + 1 < nT) load_pair(tr + 1);  // in flight during the transform
+        fft_pencil<T, N, E, +1, LdsPencil<T>, true>(y, t, lds, tw_s);
+        if constexpr (MODE == C2R_APPLY) {
+#pragma unroll
+            for (int e = 0; e < E; ++e) {
+                acc[e] += T(dm[e]) * y[e].x + T(dm[e] * dl[e]) * y[e].y;
+                dm[e] *= dl[e] * dl[e];
+            }
+        } else if constexpr (MODE == C2R_KICK) {
+            const double k0c = (tr == 0) ? sc.kappa0 : 0.0;
+            const double b0c = (tr == 0) ? sc.beta0 : 0.0;
+#pragma unroll
+            for (int e = 0; e < E; ++e) {
+                const T ca = T(k0c + double(cA[e]) * dm[e]);
+                const T cb = T(b0c + double(cB[e]) * dm[e]);
+                acc[e] += ca * y[e].x + cb * y[e].y;
+                dm[e] *= dl[e];
+            }
+        } else {
+#pragma unroll
+            for (int e = 0; e < E; ++e) {
+                for (int h = 0; h < 2; ++h) {
+                    const int sidx = 2 * tr + h;
+                    if (sidx >= nS) break;
+                    const T val = h == 0 ? y[e].x : y[e].y;
+                    if (sidx == a.M + 1) {
+                        cB[e] = val;
+                    } else {
+                        if (sidx > 0) acc[e] -= T(sc.kappa0 * dm[e]) * val;
+                        dm[e] *= dl[e];
+                    }
+                }
+            }
+        }
+    }
+
+    if constexpr (MODE == C2R_APPLY) {
+        // stage the real output (N rows x W columns) and store it coalesced
+        T* ost = reinterpret_cast<T*>(stg);
+#pragma unroll
+        for (int e = 0; e < E; ++e) ost[(t + TP * e) * W + c] = acc[e];
+        __syncthreads();
+        T* o = a.r0 + (long long)item * a.Nreal;
+        for (int i = threadIdx.x; i < N * W; i += NT) {
+            const int row = i / W, cg = col0 + i % W;
+            if (cg < a.inner) o[(long long)row * a.inner + cg] = ost[i];
+        }
+        return;
+    }
+    // kick: right-hand side, finiteness flag, forward transform, half rows out
+    cpx<T> z[E];
+    bool bad = false;
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+        T dv = acc[e];
+        if constexpr (MODE == C2R_KICK_GENERIC) dv += T(sc.lambda) * cB[e] * cB[e] * cB[e];
+        bad |= !isfinite(dv);
+        z[e] = {dv, T(0)};
+    }
+    if (bad && active) a.flag[0] = 1;
+    fft_pencil<T, N, E, -1, LdsPencil<T>, true>(z, t, lds, tw_s);
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+        const int k = t + TP * e;
+        if (k <= N / 2) {
+            cpx<T> w = z[e];
+            if (k == 0 || k == N / 2) w.y = T(0);
+            stg[k * W + c] = w;
+        }
+    }
+    __syncthreads();
+    cpx<T>* dst = a.dv_out + (long long)item * a.istride;
+    for (int i = threadIdx.x; i < HR * W; i += NT) {
+        const int row = i / W, cg = col0 + i % W;
+        if (cg < a.inner) dst[(long long)row * a.inner + cg] = stg[i];
     }
 }
 

@@ -149,8 +149,23 @@ hipError_t c2r0_mode(const C2RArgs<T>& a, int items, hipStream_t s) {
     return hipGetLastError();
 }
 
+template <typename T, int n, int E, int NW>
+hipError_t c2r0w_mode(const C2RArgs<T>& a, int items, hipStream_t s) {
+    using G = C2RW<T, n, E, NW>;
+    const dim3 grid((a.inner + G::W - 1) / G::W, items);
+    switch (a.mode) {
+        case C2R_APPLY: k_c2r0w<T, n, E, NW, C2R_APPLY><<<grid, dim3(G::NT), 0, s>>>(a); break;
+        case C2R_KICK: k_c2r0w<T, n, E, NW, C2R_KICK><<<grid, dim3(G::NT), 0, s>>>(a); break;
+        case C2R_KICK_GENERIC: k_c2r0w<T, n, E, NW, C2R_KICK_GENERIC><<<grid, dim3(G::NT), 0, s>>>(a); break;
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
 // variants: 0 -> (W, 8); 1 -> (W, 16); 2 -> (W/2, 8); 3 -> (W, 8) held to
 // 4 waves per SIMD (two workgroups per CU, registers spill); 4 -> (W/2, 16);
+// 5 -> wave-local transforms (k_c2r0w, E = 8, 4 waves; FP32, not for export);
+// 6 -> k_c2r0w with E = 8, 8 waves;
 // W = c2r_width
 template <typename T>
 hipError_t Launch<T>::c2r0(int N, const C2RArgs<T>& a, int items, hipStream_t s, int variant) {
@@ -164,6 +179,10 @@ hipError_t Launch<T>::c2r0(int N, const C2RArgs<T>& a, int items, hipStream_t s,
         if (variant == 2 && W2 != W) return c2r0_mode<T, n, E, W2, 1>(a, items, s);     \
         if (variant == 3 && W * (n / E) <= 512) return c2r0_mode<T, n, E, W, 4>(a, items, s); \
         if (variant == 4 && E2 != E && W2 != W) return c2r0_mode<T, n, E2, W2, 1>(a, items, s); \
+        if constexpr (C2RW<T, n, 8, 4>::ok && sizeof(T) == 4)                           \
+            if (variant == 5 && a.mode != C2R_EXPORT) return c2r0w_mode<T, n, 8, 4>(a, items, s); \
+        if constexpr (C2RW<T, n, 8, 8>::ok && sizeof(T) == 4)                           \
+            if (variant == 6 && a.mode != C2R_EXPORT) return c2r0w_mode<T, n, 8, 8>(a, items, s); \
         return c2r0_mode<T, n, E, W, 1>(a, items, s);                                   \
     }
         VOFL_MULTI_SIZES(C_)
