@@ -104,7 +104,8 @@ template <typename T, int N>
 constexpr int c2r_width() {
     constexpr int col = N * int(sizeof(cpx<T>));
     constexpr int w = (16 * col <= 67584) ? 16 : (8 * col <= 67584) ? 8 : 4;
-    constexpr int lim = (4096 / N) < 4 ? 4 : (4096 / N);
+    constexpr int e = (N % 3 == 0) ? 12 : (N < 8 ? N : 8);  // elements per thread of k_c2r0
+    constexpr int lim = (512 / (N / e)) < 1 ? 1 : (512 / (N / e));
     return w < lim ? w : lim;
 }
 
@@ -684,7 +685,8 @@ struct C2RW {
     static constexpr int NT = 64 * NW;
     static constexpr int ST = (HR * W + NT - 1) / NT;  // staged elements per thread per slot
     static constexpr int FPW = N + N / 8 + 16;         // one column's exchange region (padded)
-    static constexpr bool ok = (N % E == 0) && (TP <= 64) && (64 % TP == 0) && (TP >= 4);
+    static constexpr bool ok = (N % E == 0) && (TP <= 64) && (64 % TP == 0) && (TP >= 4) &&
+                               (num_stages(N, E) > 0);
 };
 
 template <typename T, int N, int E_, int NW_, int MODE>

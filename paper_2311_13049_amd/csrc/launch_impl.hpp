@@ -5,8 +5,8 @@
 
 namespace vofl {
 
-#define VOFL_MULTI_SIZES(X) X(8) X(16) X(32) X(64) X(128) X(256) X(512) X(1024)
-#define VOFL_1D_SIZES(X) X(8) X(16) X(32) X(64) X(128) X(256) X(512) X(1024) X(2048) X(4096)
+#define VOFL_MULTI_SIZES(X) X(8) X(16) X(32) X(48) X(64) X(96) X(128) X(256) X(512) X(768) X(1024)
+#define VOFL_1D_SIZES(X) X(8) X(16) X(32) X(48) X(64) X(96) X(128) X(256) X(512) X(768) X(1024) X(2048) X(4096)
 
 template <typename T>
 bool Launch<T>::supported_multi(int N) {
@@ -162,23 +162,19 @@ hipError_t c2r0w_mode(const C2RArgs<T>& a, int items, hipStream_t s) {
     return hipGetLastError();
 }
 
-// variants: 0 -> (W, 8); 1 -> (W, 16); 2 -> (W/2, 8); 3 -> (W, 8) held to
-// 4 waves per SIMD (two workgroups per CU, registers spill); 4 -> (W/2, 16);
-// 5 -> wave-local transforms (k_c2r0w, E = 8, 4 waves; FP32, not for export);
-// 6 -> k_c2r0w with E = 8, 8 waves;
-// W = c2r_width
+// variants of the axis-0 kernel: 0 -> k_c2r0 (W columns, direct register
+// loads); 2 -> k_c2r0 with W/2 columns; 5 -> k_c2r0w (wave-local
+// transforms, E = 8, 4 waves); 6 -> k_c2r0w with 8 waves. Variants 5 and 6
+// exist for FP32 lengths without a factor 3 and not for the export mode;
+// elsewhere they fall back to variant 0.
 template <typename T>
 hipError_t Launch<T>::c2r0(int N, const C2RArgs<T>& a, int items, hipStream_t s, int variant) {
     switch (N) {
 #define C_(n)                                                                           \
     case n: {                                                                           \
         constexpr int W = c2r_width<T, n>(), E = e_c2r0(n);                             \
-        constexpr int E2 = (n >= 16) ? 16 : E;                                          \
         constexpr int W2 = (W >= 8) ? W / 2 : W;                                        \
-        if (variant == 1 && E2 != E) return c2r0_mode<T, n, E2, W, 1>(a, items, s);     \
         if (variant == 2 && W2 != W) return c2r0_mode<T, n, E, W2, 1>(a, items, s);     \
-        if (variant == 3 && W * (n / E) <= 512) return c2r0_mode<T, n, E, W, 4>(a, items, s); \
-        if (variant == 4 && E2 != E && W2 != W) return c2r0_mode<T, n, E2, W2, 1>(a, items, s); \
         if constexpr (C2RW<T, n, 8, 4>::ok && sizeof(T) == 4)                           \
             if (variant == 5 && a.mode != C2R_EXPORT) return c2r0w_mode<T, n, 8, 4>(a, items, s); \
         if constexpr (C2RW<T, n, 8, 8>::ok && sizeof(T) == 4)                           \

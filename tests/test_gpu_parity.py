@@ -45,6 +45,8 @@ CASES_ND = [
     ((16, 8, 32), (-2.0, -1.0, -4.0), (2.0, 1.0, 4.0)),  # 3D mixed sizes
     ((8, 16, 16), (-1.0, -2.0, -2.0), (1.0, 2.0, 2.0)),  # 3D, single-stage axis 0
     ((32, 32, 32), (-4.0,) * 3, (4.0,) * 3),       # 3D cube
+    ((48, 96), (-3.0, -6.0), (3.0, 6.0)),          # radix-3 lengths (48 = 3*16, 96 = 3*32)
+    ((96, 16, 48), (-6.0, -1.0, -3.0), (6.0, 1.0, 3.0)),  # radix 3 on axes 0 and 2
 ]
 
 
@@ -113,6 +115,24 @@ def test_apply_constant_order_single_mode_exact():
 # step (3.13) for (1.1)
 # --------------------------------------------------------------------------
 
+@pytest.mark.parametrize("n", [96, 768])
+def test_apply_and_step_1d_radix3(n):
+    # h = 1/8 as in the 1D workload: the operator's amplification of FFT
+    # rounding (|mu_max|^{2s}) stays where FP64 parity of 1e-12 is meaningful
+    L = n / 16.0
+    lo, hi = (-L,), (L,)
+    x = grid_1d(n, lo[0], hi[0])
+    gamma = 0.1 + 0.08 * np.sin(np.pi * x / L)
+    u0 = np.exp(-x * x)
+    p = _plan((n,), lo, hi, "fp64", gamma=gamma, M=10, dt=2e-3)
+    out = host(p.apply(1, dev(u0, "fp64")))
+    assert rel_l2(out, O.mterm_apply(u0, 1.0 + gamma, lo, hi, 10)) <= 1e-12
+    u, v = dev(u0, "fp64"), dev(np.zeros(n), "fp64")
+    p.step(u, v, 20)
+    ru, _ = O.tsfp2_seismic(u0, np.zeros(n), gamma, 1.0, 1.0, lo, hi, 10, 2e-3, 20)
+    assert rel_l2(host(u), ru) <= 1e-12
+
+
 @pytest.mark.parametrize("precision", ["fp64", "fp32"])
 def test_step_1d_c1(precision):
     c = c1_inputs()
@@ -129,6 +149,8 @@ def test_step_1d_c1(precision):
 
 STEP_CASES = [
     ((64, 32), (-8.0, -4.0), (8.0, 4.0), 8, 12),
+    ((96, 48), (-6.0, -3.0), (6.0, 3.0), 6, 7),
+    ((48, 32, 96), (-3.0, -2.0, -6.0), (3.0, 2.0, 6.0), 5, 3),
     ((16, 8), (-2.0, -1.0), (2.0, 1.0), 4, 5),
     ((16, 16, 32), (-2.0, -2.0, -4.0), (2.0, 2.0, 4.0), 6, 6),
     ((8, 32, 8), (-1.0, -4.0, -1.0), (1.0, 4.0, 1.0), 3, 4),
