@@ -81,6 +81,10 @@ typedef struct vofl_desc {
     int coef_per_solve;  /* 0: one coefficient field (Q, gamma or s: N values) shared by
                             all solves; 1: batch fields (batch * N values), one per solve */
     size_t hbm_budget;   /* bytes of device memory the plan may take; 0 = no limit     */
+    int tune_steps;      /* 0: default kernel variants; > 0: vofl_plan times each
+                            candidate tile/radix variant over this many steps on
+                            temporary buffers and keeps the fastest (cached in the
+                            file named by VOFL_TUNE_CACHE, when set)                 */
 } vofl_desc;
 
 typedef struct vofl_plan_s* vofl_plan_t;
@@ -121,10 +125,20 @@ int vofl_step(vofl_plan_t plan, void* u, void* v, int nsteps, void* stream);
 int vofl_solve(vofl_plan_t plan, const void* u0, const void* v0, int nsteps,
                void* u, void* v, void* stream);
 
+/* vofl_step replayed from a HIP graph (for callers that step the same
+ * buffers repeatedly). The first call with a given (u, v, nsteps) captures
+ * vofl_step's launch sequence on an internal stream into a graph and
+ * instantiates it; every call then launches the graph on stream. The
+ * library allocates no device memory here (the HIP runtime keeps the
+ * instantiated graph). Up to 8 graphs are kept per plan. Results equal
+ * vofl_step's bit for bit. */
+int vofl_step_graph(vofl_plan_t plan, void* u, void* v, int nsteps, void* stream);
+
 /* Advance several independent solves, one plan each, by nsteps[i] steps,
- * issuing the launches of all solves interleaved on one stream so the
- * device overlaps them. Plans may differ in grid, M and precision. Each
- * solve's result equals what vofl_step gives for it alone. */
+ * each plan on an internal stream forked from (and joined back into)
+ * stream, so the device overlaps their work. Plans may differ in grid, M
+ * and precision. Each solve's result equals what vofl_step gives for it
+ * alone, bit for bit. */
 int vofl_step_batch(vofl_plan_t* plans, void** u, void** v, const int* nsteps,
                     int count, void* stream);
 
@@ -141,7 +155,8 @@ int vofl_kernel_times(vofl_plan_t plan, const char** names, double* ms,
                       long long* launches, int cap);
 
 /* Plan scalars (FP64): out[0] = gbar (or s0), out[1] = kappa0, out[2] = beta0,
- * out[3] = N, out[4] = device bytes held. Returns VOFL_OK. */
+ * out[3] = N, out[4] = device bytes held, out[5] = axis-0 kernel variant,
+ * out[6] = middle-axis kernel variant. Returns VOFL_OK. */
 int vofl_plan_info(vofl_plan_t plan, double* out, int cap);
 
 int vofl_destroy(vofl_plan_t plan);

@@ -28,6 +28,8 @@ struct Launch {
     static int tile_w(int N);
     static int c2r_w(int N);
     static int c2r_tile(int N, int variant);
+    // whether an axis-0 variant has its own kernel for length N (else it falls back to 0)
+    static bool c2r_variant_exists(int N, int variant);
     template <typename TI>
     static hipError_t contig(int N, const ContigArgs<T, TI>& a, int items, hipStream_t s);
     static hipError_t mid(int N, int dir, const MidArgs<T>& a, int planes, int items, hipStream_t s,

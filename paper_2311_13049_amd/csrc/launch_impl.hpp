@@ -188,6 +188,24 @@ hipError_t Launch<T>::c2r0(int N, const C2RArgs<T>& a, int items, hipStream_t s,
 }
 
 template <typename T>
+bool Launch<T>::c2r_variant_exists(int N, int variant) {
+    switch (N) {
+#define C_(n)                                                                           \
+    case n: {                                                                           \
+        constexpr int W = c2r_width<T, n>();                                            \
+        if (variant == 0) return true;                                                  \
+        if (variant == 2) return W >= 8;                                                \
+        if (variant == 5) return C2RW<T, n, 8, 4>::ok && sizeof(T) == 4;                \
+        if (variant == 6) return C2RW<T, n, 8, 8>::ok && sizeof(T) == 4;                \
+        return false;                                                                   \
+    }
+        VOFL_MULTI_SIZES(C_)
+#undef C_
+        default: return false;
+    }
+}
+
+template <typename T>
 int Launch<T>::c2r_tile(int N, int variant) {
     switch (N) {
 #define C_(n)                                                                           \

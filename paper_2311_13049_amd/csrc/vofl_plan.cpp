@@ -18,7 +18,9 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <fstream>
 #include <map>
+#include <sstream>
 #include <string>
 #include <vector>
 
@@ -96,6 +98,7 @@ int derive(const vofl_desc* d, Geometry& g) {
     if (d->batch < 0 || d->batch > 4096) return fail(VOFL_ERR_INVALID, "batch out of range");
     if (d->coef_per_solve != 0 && d->coef_per_solve != 1)
         return fail(VOFL_ERR_INVALID, "coef_per_solve must be 0 or 1");
+    if (d->tune_steps < 0 || d->tune_steps > 1000) return fail(VOFL_ERR_INVALID, "tune_steps must be in [0, 1000]");
     g.batch = d->batch ? d->batch : 1;
     g.max_batch = d->max_batch ? d->max_batch : 1;
     g.ncoef = d->coef_per_solve ? g.batch : 1;
@@ -195,7 +198,15 @@ struct vofl_plan_s {
     void* work = nullptr;
     int* flag = nullptr;
     std::vector<void*> allocs;
-    int c2r_variant = 0;               // k_c2r0 tile variant
+    int c2r_variant = 0;               // axis-0 kernel variant (see Launch::c2r0)
+    double tuned_ms = 0;               // best time per tuning run (0: not tuned)
+    struct GraphEntry {
+        void* u;
+        void* v;
+        int nsteps;
+        hipGraphExec_t exec;
+    };
+    std::vector<GraphEntry> graphs;    // vofl_step_graph cache, oldest first
     int mid_variant = 1;               // k_mid tile variant (1: double-width tiles)
     hipStream_t own_stream = nullptr;  // used by vofl_step_batch
     hipEvent_t fork_ev = nullptr, join_ev = nullptr;
@@ -212,6 +223,7 @@ struct vofl_plan_s {
             pool.push_back(r.b);
         }
         for (auto e : pool) (void)hipEventDestroy(e);
+        for (auto& gr : graphs) (void)hipGraphExecDestroy(gr.exec);
         if (fork_ev) (void)hipEventDestroy(fork_ev);
         if (join_ev) (void)hipEventDestroy(join_ev);
         if (own_stream) (void)hipStreamDestroy(own_stream);
@@ -580,6 +592,115 @@ int step_any(vofl_plan_s* p, void* u, void* v, int nsteps, hipStream_t s) {
 }  // namespace
 
 // ---------------------------------------------------------------------------
+// autotuning of the axis-0 and middle-axis kernel variants
+// ---------------------------------------------------------------------------
+std::string tune_key(const vofl_plan_s* p) {
+    std::ostringstream k;
+    k << "vofl1 ndim=" << p->g.ndim << " n=" << p->g.n[0] << "x" << p->g.n[1] << "x" << p->g.n[2]
+      << " M=" << p->M << " prec=" << p->precision << " model=" << p->model << " batch=" << p->g.batch;
+    return k.str();
+}
+
+bool tune_cache_lookup(vofl_plan_s* p, const std::string& key) {
+    const char* path = std::getenv("VOFL_TUNE_CACHE");
+    if (!path) return false;
+    std::ifstream f(path);
+    std::string line;
+    bool found = false;
+    while (std::getline(f, line)) {
+        const size_t bar = line.find(" | ");
+        if (bar == std::string::npos || line.substr(0, bar) != key) continue;
+        std::istringstream rest(line.substr(bar + 3));
+        int c = 0, m = 0;
+        double ms = 0;
+        if (rest >> c >> m >> ms) {
+            p->c2r_variant = c;
+            p->mid_variant = m;
+            p->tuned_ms = ms;
+            found = true;  // the last matching line wins
+        }
+    }
+    return found;
+}
+
+// Time each candidate over `steps` TSFP2 steps on temporary zero fields and
+// keep the fastest. Runs inside vofl_plan (the only place that allocates).
+template <typename T>
+int autotune(vofl_plan_s* p, int steps) {
+    const Geometry& g = p->g;
+    if (g.ndim < 2) return VOFL_OK;
+    const std::string key = tune_key(p);
+    if (tune_cache_lookup(p, key)) return VOFL_OK;
+    const size_t bytes = (size_t)g.batch * g.Nreal * sizeof(T);
+    T* u = nullptr;
+    T* v = nullptr;
+    hipStream_t s = nullptr;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    hipError_t e = hipMalloc(&u, bytes);
+    if (e == hipSuccess) e = hipMalloc(&v, bytes);
+    if (e == hipSuccess) e = hipMemset(u, 0, bytes);
+    if (e == hipSuccess) e = hipMemset(v, 0, bytes);
+    if (e == hipSuccess) e = hipDeviceSynchronize();  // zero fields and tables in place before s runs
+    if (e == hipSuccess) e = hipStreamCreateWithFlags(&s, hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipEventCreate(&e0);
+    if (e == hipSuccess) e = hipEventCreate(&e1);
+    int rc = (e == hipSuccess) ? VOFL_OK : hip_fail(e, "autotune setup");
+    std::vector<int> c2r, mid;
+    for (int c : {0, 2, 5, 6})
+        if (Launch<T>::c2r_variant_exists(g.n[0], c)) c2r.push_back(c);
+    mid.push_back(0);
+    if (g.ndim == 3 && Launch<T>::mid_tile(g.n[1], 1) != Launch<T>::mid_tile(g.n[1], 0)) mid.push_back(1);
+    const bool timing = p->timing;
+    p->timing = false;
+    double best = 1e300;
+    int bc = p->c2r_variant, bm = p->mid_variant;
+    for (int c : c2r) {
+        for (int m : mid) {
+            if (rc) break;
+            p->c2r_variant = c;
+            p->mid_variant = m;
+            rc = step_any<T>(p, u, v, 1, s);
+            if (rc) break;
+            (void)hipEventRecord(e0, s);
+            rc = step_any<T>(p, u, v, steps, s);
+            (void)hipEventRecord(e1, s);
+            if (rc) break;
+            e = hipEventSynchronize(e1);
+            if (e != hipSuccess) {
+                rc = hip_fail(e, "autotune run");
+                break;
+            }
+            float ms = 0.f;
+            (void)hipEventElapsedTime(&ms, e0, e1);
+            if (ms < best) {
+                best = ms;
+                bc = c;
+                bm = m;
+            }
+        }
+    }
+    p->timing = timing;
+    p->c2r_variant = bc;
+    p->mid_variant = bm;
+    p->tuned_ms = (best < 1e300) ? best / steps : 0.0;
+    if (s) (void)hipStreamSynchronize(s);
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    if (s) (void)hipStreamDestroy(s);
+    if (u) (void)hipFree(u);
+    if (v) (void)hipFree(v);
+    (void)hipMemset(p->flag, 0, 256);
+    (void)hipDeviceSynchronize();
+    if (rc == VOFL_OK) {
+        if (const char* path = std::getenv("VOFL_TUNE_CACHE")) {
+            std::ofstream f(path, std::ios::app);
+            f << key << " | " << bc << " " << bm << " " << p->tuned_ms << "\n";
+        }
+    }
+    return rc;
+}
+
+// ---------------------------------------------------------------------------
 // C ABI
 // ---------------------------------------------------------------------------
 extern "C" {
@@ -668,6 +789,8 @@ int vofl_plan(const vofl_desc* d, void* stream, vofl_plan_t* out) {
     if (const char* ev = std::getenv("VOFL_MID_VARIANT")) p->mid_variant = std::atoi(ev);
     rc = (d->precision == VOFL_FP32) ? upload_tables<float>(p, delta, A, B)
                                      : upload_tables<double>(p, delta, A, B);
+    if (rc == VOFL_OK && d->tune_steps > 0)
+        rc = (d->precision == VOFL_FP32) ? autotune<float>(p, d->tune_steps) : autotune<double>(p, d->tune_steps);
     if (rc) {
         delete p;
         return rc;
@@ -706,6 +829,54 @@ int vofl_step(vofl_plan_t p, void* u, void* v, int nsteps, void* stream) {
     hipStream_t s = (hipStream_t)stream;
     return p->precision == VOFL_FP32 ? step_any<float>(p, u, v, nsteps, s)
                                      : step_any<double>(p, u, v, nsteps, s);
+}
+
+int vofl_step_graph(vofl_plan_t p, void* u, void* v, int nsteps, void* stream) {
+    if (!p) return fail(VOFL_ERR_INVALID, "plan is NULL");
+    if (!u || !v) return fail(VOFL_ERR_INVALID, "u and v must be device pointers");
+    if (u == v) return fail(VOFL_ERR_INVALID, "u and v must be distinct");
+    if (nsteps < 0) return fail(VOFL_ERR_INVALID, "nsteps must be >= 0");
+    hipStream_t s = (hipStream_t)stream;
+    for (auto& gr : p->graphs)
+        if (gr.u == u && gr.v == v && gr.nsteps == nsteps) {
+            hipError_t e = hipGraphLaunch(gr.exec, s);
+            return e == hipSuccess ? VOFL_OK : hip_fail(e, "graph launch");
+        }
+    hipError_t e = hipSuccess;
+    if (!p->own_stream) {
+        e = hipStreamCreateWithFlags(&p->own_stream, hipStreamNonBlocking);
+        if (e == hipSuccess) e = hipEventCreateWithFlags(&p->join_ev, hipEventDisableTiming);
+        if (e != hipSuccess) return hip_fail(e, "stream");
+    }
+    const bool timing = p->timing;
+    p->timing = false;  // no event records inside the graph
+    e = hipStreamBeginCapture(p->own_stream, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess) {
+        p->timing = timing;
+        return hip_fail(e, "begin capture");
+    }
+    int rc = p->precision == VOFL_FP32 ? step_any<float>(p, u, v, nsteps, p->own_stream)
+                                       : step_any<double>(p, u, v, nsteps, p->own_stream);
+    hipGraph_t graph = nullptr;
+    e = hipStreamEndCapture(p->own_stream, &graph);
+    p->timing = timing;
+    if (rc) {
+        if (graph) (void)hipGraphDestroy(graph);
+        return rc;
+    }
+    if (e != hipSuccess) return hip_fail(e, "end capture");
+    hipGraphExec_t exec = nullptr;
+    e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    if (e != hipSuccess) return hip_fail(e, "graph instantiate");
+    if (p->graphs.size() >= 8) {
+        (void)hipDeviceSynchronize();  // the oldest graph may still be running
+        (void)hipGraphExecDestroy(p->graphs.front().exec);
+        p->graphs.erase(p->graphs.begin());
+    }
+    p->graphs.push_back({u, v, nsteps, exec});
+    e = hipGraphLaunch(exec, s);
+    return e == hipSuccess ? VOFL_OK : hip_fail(e, "graph launch");
 }
 
 int vofl_solve(vofl_plan_t p, const void* u0, const void* v0, int nsteps, void* u, void* v, void* stream) {
@@ -792,9 +963,10 @@ int vofl_kernel_times(vofl_plan_t p, const char** names, double* ms, long long* 
 
 int vofl_plan_info(vofl_plan_t p, double* out, int cap) {
     if (!p || !out) return fail(VOFL_ERR_INVALID, "null argument");
-    const double v[5] = {p->model == VOFL_MODEL_GENERIC ? p->sc_host[0].sig1 : p->sc_host[0].sig1 - 1.0,
-                         p->sc_host[0].kappa0, p->sc_host[0].beta0, (double)p->g.Nreal, (double)p->g.bytes};
-    for (int i = 0; i < cap && i < 5; ++i) out[i] = v[i];
+    const double v[7] = {p->model == VOFL_MODEL_GENERIC ? p->sc_host[0].sig1 : p->sc_host[0].sig1 - 1.0,
+                         p->sc_host[0].kappa0, p->sc_host[0].beta0, (double)p->g.Nreal, (double)p->g.bytes,
+                         (double)p->c2r_variant, (double)p->mid_variant};
+    for (int i = 0; i < cap && i < 7; ++i) out[i] = v[i];
     return VOFL_OK;
 }
 

@@ -31,7 +31,7 @@ VOFL_OP_S2 = 2
 
 # every function declared in include/vofl.h
 ABI_FUNCTIONS = (
-    "vofl_plan", "vofl_plan_footprint", "vofl_apply", "vofl_step", "vofl_solve",
+    "vofl_plan", "vofl_plan_footprint", "vofl_apply", "vofl_step", "vofl_step_graph", "vofl_solve",
     "vofl_step_batch", "vofl_sync_status", "vofl_set_timing", "vofl_kernel_times",
     "vofl_plan_info", "vofl_destroy", "vofl_last_error", "vofl_version",
 )
@@ -60,6 +60,7 @@ class vofl_desc(ctypes.Structure):
         ("batch", ctypes.c_int),
         ("coef_per_solve", ctypes.c_int),
         ("hbm_budget", ctypes.c_size_t),
+        ("tune_steps", ctypes.c_int),
     ]
 
 
@@ -86,6 +87,7 @@ def load_library():
     lib.vofl_plan_footprint.argtypes = [ctypes.POINTER(vofl_desc), ctypes.POINTER(ctypes.c_size_t)]
     lib.vofl_apply.argtypes = [vp, ctypes.c_int, vp, vp, ctypes.c_int, vp]
     lib.vofl_step.argtypes = [vp, vp, vp, ctypes.c_int, vp]
+    lib.vofl_step_graph.argtypes = [vp, vp, vp, ctypes.c_int, vp]
     lib.vofl_solve.argtypes = [vp, vp, vp, ctypes.c_int, vp, vp, vp]
     lib.vofl_step_batch.argtypes = [ctypes.POINTER(vp), ctypes.POINTER(vp), ctypes.POINTER(vp),
                                     ctypes.POINTER(ctypes.c_int), ctypes.c_int, vp]
@@ -97,7 +99,7 @@ def load_library():
     lib.vofl_destroy.argtypes = [vp]
     lib.vofl_last_error.restype = ctypes.c_char_p
     lib.vofl_version.restype = ctypes.c_char_p
-    for name in ("vofl_plan", "vofl_plan_footprint", "vofl_apply", "vofl_step", "vofl_solve",
+    for name in ("vofl_plan", "vofl_plan_footprint", "vofl_apply", "vofl_step", "vofl_step_graph", "vofl_solve",
                  "vofl_step_batch", "vofl_sync_status", "vofl_set_timing", "vofl_kernel_times",
                  "vofl_plan_info", "vofl_destroy"):
         getattr(lib, name).restype = ctypes.c_int
@@ -114,7 +116,7 @@ def _check(rc: int) -> int:
 
 def make_desc(shape, lo, hi, *, model="seismic", c0=1.0, omega0=1.0, Q=None, gamma=None,
               s=None, kappa=1.0, lam=0.0, M=8, dt=1e-3, precision="fp64", max_batch=1,
-              batch=1, coef_per_solve=False, hbm_budget=0):
+              batch=1, coef_per_solve=False, hbm_budget=0, tune_steps=0):
     """Build a vofl_desc; returns (desc, keepalive) where keepalive holds the host arrays."""
     shape = tuple(int(n) for n in shape)
     d = vofl_desc()
@@ -145,6 +147,7 @@ def make_desc(shape, lo, hi, *, model="seismic", c0=1.0, omega0=1.0, Q=None, gam
     d.batch = int(batch)
     d.coef_per_solve = 1 if coef_per_solve else 0
     d.hbm_budget = int(hbm_budget)
+    d.tune_steps = int(tune_steps)
     return d, keep
 
 
@@ -170,6 +173,11 @@ def vofl_apply(plan: int, op: int, u_ptr: int, out_ptr: int, nfields: int, strea
 def vofl_step(plan: int, u_ptr: int, v_ptr: int, nsteps: int, stream=0) -> None:
     _check(load_library().vofl_step(ctypes.c_void_p(plan), ctypes.c_void_p(u_ptr),
                                     ctypes.c_void_p(v_ptr), nsteps, ctypes.c_void_p(stream)))
+
+
+def vofl_step_graph(plan: int, u_ptr: int, v_ptr: int, nsteps: int, stream=0) -> None:
+    _check(load_library().vofl_step_graph(ctypes.c_void_p(plan), ctypes.c_void_p(u_ptr),
+                                          ctypes.c_void_p(v_ptr), nsteps, ctypes.c_void_p(stream)))
 
 
 def vofl_solve(plan: int, u0_ptr: int, v0_ptr: int, nsteps: int, u_ptr: int, v_ptr: int,
@@ -207,10 +215,10 @@ def vofl_kernel_times(plan: int) -> dict:
 
 
 def vofl_plan_info(plan: int) -> dict:
-    out = (ctypes.c_double * 5)()
-    _check(load_library().vofl_plan_info(ctypes.c_void_p(plan), out, 5))
+    out = (ctypes.c_double * 7)()
+    _check(load_library().vofl_plan_info(ctypes.c_void_p(plan), out, 7))
     return dict(mean_order_offset=out[0], kappa0=out[1], beta0=out[2], N=int(out[3]),
-                device_bytes=int(out[4]))
+                device_bytes=int(out[4]), c2r_variant=int(out[5]), mid_variant=int(out[6]))
 
 
 def vofl_destroy(plan: int) -> None:
@@ -271,6 +279,12 @@ class Plan:
         self._check_tensor(u, self.batch, "u")
         self._check_tensor(v, self.batch, "v")
         vofl_step(self.handle, u.data_ptr(), v.data_ptr(), int(nsteps), self._stream())
+        return u, v
+
+    def step_graph(self, u, v, nsteps: int):
+        self._check_tensor(u, self.batch, "u")
+        self._check_tensor(v, self.batch, "v")
+        vofl_step_graph(self.handle, u.data_ptr(), v.data_ptr(), int(nsteps), self._stream())
         return u, v
 
     def solve(self, u0, v0, nsteps: int):
