@@ -25,7 +25,7 @@ import numpy as np
 __all__ = [
     "BASE_SEED", "rng_for", "grid_1d", "mesh", "gaussian_pulse", "grf_Q",
     "two_layer_Q", "c1_inputs", "c2_inputs", "c3_inputs", "c4_inputs",
-    "c5_requests", "paper_s1", "paper_s2", "paper_ex1_initial",
+    "c5_requests", "c5_request_inputs", "paper_s1", "paper_s2", "paper_ex1_initial",
 ]
 
 BASE_SEED = 13049
@@ -156,6 +156,25 @@ def c5_requests(count: int = 200, rate: float = 200.0, grids=None, seed_offset: 
                          precision=("fp32" if rng.random() < 0.5 else "fp64"),
                          seed=int(rng.integers(1 << 31))))
     return reqs
+
+
+def c5_request_inputs(req):
+    """Box, time step, Q field and initial data of one request of the stream.
+
+    2D grids live on [-32,32)^2 with dt = 5e-4, 3D grids on [-16,16)^3 with
+    dt = 1e-3; Q is a Gaussian random field (correlation length 4, Q in
+    [10, 200]); u0 is a unit Gaussian pulse at a uniform random centre, v0 = 0.
+    """
+    shape = tuple(int(n) for n in req["shape"])
+    d = len(shape)
+    half = 32.0 if d == 2 else 16.0
+    lo, hi = (-half,) * d, (half,) * d
+    rng = rng_for(5, 1, int(req["seed"]))
+    Q = grf_Q(shape, lo, hi, rng, corr_len=4.0)
+    xs = rng.uniform(-half, half, size=d)
+    u0 = gaussian_pulse(shape, lo, hi, xs)
+    return dict(shape=shape, lo=lo, hi=hi, dt=(5e-4 if d == 2 else 1e-3), Q=Q, u0=u0,
+                v0=np.zeros_like(u0), c0=1.0, omega0=1.0)
 
 
 def paper_s1(x):
