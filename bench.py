@@ -2,7 +2,14 @@
 M = 16, FP32 transforms (FP64 expansion coefficients, multipliers,
 propagator and spectral state), one MI355X.
 
-python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu]
+python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--workload c3|c4|c5]
+
+The default workload (c3) is the 256^3 grid below. Two more measurements
+print their own JSON line: c4, the batched shots (64 x 512^2 sharing one Q
+and 16 x 768^2 with their own Q, M = 12, FP32) as eager batched steps and as
+graph replays, against the plain FP64 path solving one shot at a time; c5,
+the request server on a Poisson request stream against the same plain path
+serving one request at a time.
 
 One step is the whole hot path: the exact damped-oscillator sub-steps and
 the kick, which applies both variable-order operators (2.13) (L1 to u and L2
@@ -30,10 +37,12 @@ WORKLOAD = ("3D periodic [-16,16)^3, 256^3, M=16, two-layer Q (20 above / 100 be
 
 
 def kernel_source_hash() -> str:
+    """Hash of the device-code sources (kernels and their launch shapes); host
+    code does not change what a kernel reads or writes."""
     h = hashlib.sha256()
     csrc = os.path.join(ROOT, "paper_2311_13049_amd", "csrc")
     for name in sorted(os.listdir(csrc)):
-        if name.endswith((".hpp", ".hip", ".cpp")):
+        if name.endswith((".hpp", ".hip")):
             with open(os.path.join(csrc, name), "rb") as f:
                 h.update(f.read())
     return h.hexdigest()[:16]
@@ -70,6 +79,8 @@ def main():
     ap.add_argument("--M", type=int, default=16)
     ap.add_argument("--precision", default="fp32")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--workload", default="c3", choices=("c3", "c4", "c5"))
+    ap.add_argument("--requests", type=int, default=40, help="c5: requests in the trace")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain device copy of 1 GiB five times (HBM counter calibration)")
     args = ap.parse_args()
@@ -96,6 +107,10 @@ def main():
         print(json.dumps({"copy_bytes_read_per_launch": nbytes, "copy_bytes_written_per_launch": nbytes,
                           "launches": 5}), flush=True)
         return
+    if args.workload == "c4":
+        return bench_c4(args, torch, V, dev)
+    if args.workload == "c5":
+        return bench_c5(args, torch, V, dev)
     n, M = args.n, args.M
     c = c3_inputs(n=n)
     prec = args.precision
@@ -188,6 +203,142 @@ def main():
         "kernel_ms_per_step": {k: ms / args.steps for k, (ms, _) in ktimes.items()},
         "status": status,
         "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+
+
+def _fork_join(torch, streams, fns):
+    """Run fns[i] on streams[i] after the current stream's work; join back."""
+    cur = torch.cuda.current_stream()
+    start = torch.cuda.Event()
+    start.record(cur)
+    for st, fn in zip(streams, fns):
+        st.wait_event(start)
+        with torch.cuda.stream(st):
+            fn(st.cuda_stream)
+    for st in streams:
+        ev = torch.cuda.Event()
+        ev.record(st)
+        cur.wait_event(ev)
+
+
+def bench_c4(args, torch, V, dev):
+    """Batched shots: whole-batch steps/s, eager and graph, vs the plain FP64 path."""
+    from workloads import c4_inputs
+    c = c4_inputs()
+    steps, warm = args.steps, args.warmup
+    groups = []
+    for big in (False, True):
+        shots = [s for s in c["shots"] if (s["shape"][0] == 768) == big]
+        Q = np.stack([s["Q"] for s in shots]) if big else shots[0]["Q"]
+        t0 = time.perf_counter()
+        plan = V.Plan(shots[0]["shape"], c["lo"], c["hi"], Q=Q, M=c["M"], dt=c["dt"], precision="fp32",
+                      c0=c["c0"], omega0=c["omega0"], batch=len(shots), coef_per_solve=big, tune_steps=5)
+        tplan = time.perf_counter() - t0
+        u = torch.from_numpy(np.stack([s["u0"] for s in shots])).to(dev, torch.float32)
+        v = torch.zeros_like(u)
+        groups.append(dict(shots=shots, plan=plan, u=u, v=v, plan_s=tplan, info=plan.info()))
+    streams = [torch.cuda.Stream() for _ in groups]
+    hs = [g["plan"].handle for g in groups]
+
+    def eager(k):
+        V.vofl_step_batch(hs, [g["u"].data_ptr() for g in groups], [g["v"].data_ptr() for g in groups],
+                          [k] * len(groups), torch.cuda.current_stream().cuda_stream)
+
+    def graph(k):
+        _fork_join(torch, streams, [
+            (lambda s, g=g: V.vofl_step_graph(g["plan"].handle, g["u"].data_ptr(), g["v"].data_ptr(), k, s))
+            for g in groups])
+
+    timings = {}
+    for name, fn in (("eager_batch", eager), ("graph_batch", graph)):
+        fn(warm)
+        if name == "graph_batch":
+            fn(steps)  # capture outside the timed region
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        fn(steps)
+        torch.cuda.synchronize()
+        timings[name] = time.perf_counter() - t0
+    status = [g["plan"].sync_status() for g in groups]
+    nshots = sum(len(g["shots"]) for g in groups)
+    Ntot = sum(len(g["shots"]) * int(np.prod(g["shots"][0]["shape"])) for g in groups)
+    # algorithmic bytes of a step: (2M+3) real-field transforms, each one
+    # read and one write of the field per axis pass (2 passes in 2D)
+    bstep = (2 * c["M"] + 3) * 2 * 2 * Ntot * 4
+
+    # plain FP64 single-solve path: one shot per plan, eager vofl_step,
+    # one shot at a time; timed on two shots of each size, scaled to the batch
+    plain = {}
+    for g in groups:
+        sh = g["shots"][0]
+        p = V.Plan(sh["shape"], c["lo"], c["hi"], Q=sh["Q"], M=c["M"], dt=c["dt"], precision="fp64",
+                   c0=c["c0"], omega0=c["omega0"])
+        ts = []
+        for s_ in g["shots"][:2]:
+            u = torch.from_numpy(s_["u0"]).to(dev, torch.float64)
+            v = torch.zeros_like(u)
+            p.step(u, v, warm)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            p.step(u, v, steps)
+            torch.cuda.synchronize()
+            ts.append((time.perf_counter() - t0) / steps)
+        plain[f"{sh['shape'][0]}^2"] = float(np.mean(ts))
+        p.close()
+    plain_step = sum(len(g["shots"]) * plain[f"{g['shots'][0]['shape'][0]}^2"] for g in groups)
+    best = min(timings, key=timings.get)
+    step_s = timings[best] / steps
+    out = {
+        "metric": "batched shot-steps/s (64 x 512^2 shared Q + 16 x 768^2 own Q, M=12)",
+        "value": nshots / step_s, "unit": "shot-steps/s", "n_gpus": 1, "steps": steps, "warmup": warm,
+        "ms_per_step": step_s * 1e3, "higher_is_better": True, "dtype": "f32", "data": "synthetic",
+        "mode": best,
+        "config": {"workload": "c4 batched shots: 64 x 512^2 on [-32,32)^2 sharing one GRF Q + 16 x 768^2 "
+                               "with their own GRF Q, M=12, FP32, dt=5e-4"},
+        "ms_per_step_by_mode": {k: t / steps * 1e3 for k, t in timings.items()},
+        "applies_per_s": 2 * nshots / step_s,
+        "gpts_M_per_s": Ntot * c["M"] * 2 / step_s / 1e9,
+        "roofline": {"bound": "hbm", "achieved": bstep / step_s / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": bstep / step_s / 1e9 / HBM_PEAK_GBS, "alg_bytes_per_step": bstep},
+        "plain_fp64_single_solve": {"ms_per_step_whole_batch": plain_step * 1e3,
+                                    "ms_per_shot_step": {k: t * 1e3 for k, t in plain.items()},
+                                    "speedup_of_batched": plain_step / step_s,
+                                    "sample": "2 shots of each size, solved one at a time, scaled to 64 + 16"},
+        "plan_build_s": [g["plan_s"] for g in groups],
+        "tuned_variants": [{"c2r": g["info"]["c2r_variant"], "mid": g["info"]["mid_variant"]} for g in groups],
+        "status": status,
+    }
+    print(json.dumps(out), flush=True)
+
+
+def bench_c5(args, torch, V, dev):
+    """Request server on a Poisson trace vs the plain FP64 path, one request at a time."""
+    from paper_2311_13049_amd import serve as S
+    from workloads import c5_requests
+    t0 = time.perf_counter()
+    reqs = S.requests_from_stream(c5_requests(count=args.requests))
+    gen_s = time.perf_counter() - t0
+    print(json.dumps({"c5_inputs_ready_s": gen_s, "requests": len(reqs)}), flush=True)
+    served, st_served = S.Server(slots=16, graphs=True).run(reqs, realtime=True)
+    print(json.dumps({"served": st_served}), flush=True)
+    plain, st_plain = S.Server(slots=1, chunk=0, graphs=False, precision="fp64").run(reqs, realtime=True)
+    span = max(r.arrival for r in reqs) - min(r.arrival for r in reqs)
+    demand = sum(r.service for r in plain.values() if r.status == "ok")
+    work = sum(r.N * r.M * r.steps for r in reqs)
+    out = {
+        "metric": "served requests/s and p50/p99 latency (Poisson stream, mean 200 req/s)",
+        "value": st_served.get("requests_per_s"), "unit": "requests/s", "n_gpus": 1,
+        "higher_is_better": True, "data": "synthetic", "dtype": "mixed f32/f64 (per request)",
+        "config": {"workload": f"c5 request stream: {len(reqs)} requests, grids 128^2..1024^2 and 128^3, "
+                               "256^3, M in {8,16}, steps U{100..2000}, FP32 or FP64, GRF Q"},
+        "served": st_served,
+        "plain_fp64_single_solve": st_plain,
+        "offered_load": demand / max(span, 1e-9),
+        "offered_load_note": "GPU-seconds of the plain path per second of trace",
+        "work_gpts_M_steps": work / 1e9,
+        "speedup_requests_per_s": (st_served.get("requests_per_s") or 0) / max(st_plain.get("requests_per_s") or 1e-30, 1e-30),
+        "p99_latency_ratio_plain_over_served": (st_plain.get("p99_latency_s") or 0) / max(st_served.get("p99_latency_s") or 1e-30, 1e-30),
     }
     print(json.dumps(out), flush=True)
 

@@ -21,6 +21,7 @@
 #include <fstream>
 #include <map>
 #include <sstream>
+#include <thread>
 #include <string>
 #include <vector>
 
@@ -287,6 +288,27 @@ int dalloc(vofl_plan_s* p, P** ptr, size_t bytes) {
     return VOFL_OK;
 }
 
+// Host loops over grid points (coefficient maps) split over threads; each
+// element is computed independently, so the result does not depend on the split.
+template <class F>
+void parallel_for(long long n, F&& fn) {
+    const unsigned hw = std::thread::hardware_concurrency();
+    const long long nt = std::min<long long>(std::max(1u, std::min(hw, 16u)), std::max(1LL, n / (1LL << 16)));
+    if (nt <= 1) {
+        for (long long i = 0; i < n; ++i) fn(i);
+        return;
+    }
+    std::vector<std::thread> th;
+    const long long per = (n + nt - 1) / nt;
+    for (long long t = 0; t < nt; ++t) {
+        const long long a = t * per, b = std::min(n, a + per);
+        th.emplace_back([a, b, &fn] {
+            for (long long i = a; i < b; ++i) fn(i);
+        });
+    }
+    for (auto& x : th) x.join();
+}
+
 template <typename T>
 int upload_tables(vofl_plan_s* p, const std::vector<double>& delta, const std::vector<double>& A,
                   const std::vector<double>& B) {
@@ -319,10 +341,10 @@ int upload_tables(vofl_plan_s* p, const std::vector<double>& delta, const std::v
     }
     const size_t ncv = delta.size();
     std::vector<T> At(ncv), Bt(ncv);
-    for (size_t i = 0; i < ncv; ++i) {
+    parallel_for((long long)ncv, [&](long long i) {
         At[i] = T(A[i]);
         Bt[i] = T(B[i]);
-    }
+    });
     int rc;
     if ((rc = dalloc(p, &p->delta, ncv * sizeof(double)))) return rc;
     if ((rc = dalloc(p, (T**)&p->A, ncv * sizeof(T)))) return rc;
@@ -740,11 +762,11 @@ int vofl_plan(const vofl_desc* d, void* stream, vofl_plan_t* out) {
     for (int c = 0; c < ncoef; ++c) {
         const long long off = (long long)c * N;
         std::vector<double> f(N);
-        for (long long i = 0; i < N; ++i) {
+        parallel_for(N, [&](long long i) {
             if (d->model == VOFL_MODEL_GENERIC) f[i] = d->s[off + i];
             else if (d->Q) f[i] = std::atan2(1.0, d->Q[off + i]) / M_PI;
             else f[i] = d->gamma[off + i];
-        }
+        });
         long double sum = 0.0L;
         for (long long i = 0; i < N; ++i) sum += f[i];
         const double mean = (double)(sum / (long double)N);
@@ -761,10 +783,10 @@ int vofl_plan(const vofl_desc* d, void* stream, vofl_plan_t* out) {
             s.beta0 = 0.0;
             s.lambda = d->lambda;
         } else {
-            for (long long i = 0; i < N; ++i) {
+            parallel_for(N, [&](long long i) {
                 delta[off + i] = f[i] - mean;
                 seismic_AB(f[i], d->c0, d->omega0, A[off + i], B[off + i]);
-            }
+            });
             double k0, b0;
             seismic_AB(mean, d->c0, d->omega0, k0, b0);
             s.sig1 = 1.0 + mean;

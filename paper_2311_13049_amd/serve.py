@@ -4,13 +4,18 @@ Requests (grid, Q field, initial data, M, step count, precision) arrive over
 time. A request is admitted as soon as a slot is free and its device
 footprint (the plan's workspace from vofl_plan_footprint plus the two
 wavefields) fits the memory budget, in arrival order. Every admitted request
-owns a HIP stream: its plan is built and its fields are uploaded by a host
-worker thread, then the main loop advances it in chunks of TSFP2 steps (each
-chunk a captured graph replay, vofl_step_graph) while other requests run on
-their own streams, so that their kernels overlap on the device. Wavefields
-stay resident in device memory for the whole solve. When the last chunk is
-done a worker reads the stability flag, downloads (u, v), destroys the plan
-and returns slot and memory to the admission queue.
+owns a HIP stream: its plan is built, its fields are uploaded from pinned
+host memory, and it is advanced in chunks of TSFP2 steps (each chunk a
+captured graph replay, vofl_step_graph) while other requests run on their own
+streams, so that their kernels overlap on the device. Wavefields stay
+resident in device memory for the whole solve; at the end (u, v) are copied
+back asynchronously and the stability flag is read.
+
+One host thread makes every HIP call: graph capture on one thread must not
+overlap device-wide calls (allocation, synchronisation, frees) made by
+another. Host-heavy work inside vofl_plan (coefficient maps) is spread over
+threads by the library itself. Finished plans are destroyed in groups, when
+memory is needed or at the end, because a free waits for the device.
 
 Each solve runs the same kernels on its own buffers with no reduction across
 solves, so a result does not depend on what else is in flight.
@@ -21,7 +26,6 @@ All computation runs in libvofl's HIP kernels; this module schedules.
 from __future__ import annotations
 
 import collections
-import concurrent.futures as cf
 import dataclasses
 import time
 
@@ -89,6 +93,16 @@ def footprint(req: Request, precision: str) -> int:
     return V.vofl_plan_footprint(desc) + 2 * req.N * elt
 
 
+def est_step_seconds(req: Request, precision: str) -> float:
+    """Rough device time of one TSFP2 step: 2M+3 real-field transforms, each
+    one read and one write of the field per axis pass, at 4 TB/s, plus a
+    floor of six kernel launches. Used only to size chunks and order work."""
+    elt = 4 if precision == "fp32" else 8
+    d = len(req.shape)
+    nbytes = (2 * req.M + 3) * 2 * d * req.N * elt
+    return nbytes / 4.0e12 + 6 * 4e-6
+
+
 class Admission:
     """First-come first-served admission under a slot count and a byte budget.
 
@@ -120,9 +134,16 @@ class Admission:
         return True
 
     def release(self, nbytes: int) -> None:
-        self.used -= nbytes
+        self.release_slot()
+        self.release_memory(nbytes)
+
+    def release_slot(self) -> None:
         self.active -= 1
-        assert self.used >= 0 and self.active >= 0
+        assert self.active >= 0
+
+    def release_memory(self, nbytes: int) -> None:
+        self.used -= nbytes
+        assert self.used >= 0
 
 
 class _Job:
@@ -133,13 +154,19 @@ class _Job:
         self.slot = slot
         self.admitted = admitted
         self.started = float("nan")
-        self.state = "preparing"
-        self.future = None
+        self.state = "running"
         self.plan = None
-        self.u = None
-        self.v = None
+        self.u = self.v = None
+        self.host = None            # pinned staging (upload, then download)
+        self.dev = None             # device (u, v) pair
         self.issued = 0
-        self.events = collections.deque()
+        self.events = collections.deque()   # (event, estimated seconds) per queued chunk
+        self.done_ev = None
+        self.step_s = est_step_seconds(req, precision)
+        self.chunk = 1
+
+    def remaining_s(self) -> float:
+        return (self.req.steps - self.issued) * self.step_s
 
 
 class Server:
@@ -147,14 +174,18 @@ class Server:
 
     slots        maximum number of requests admitted at once
     budget       device bytes for admitted requests (default: 90% of free memory)
-    chunk        TSFP2 steps per launch; 0 issues the whole solve in one call
+    chunk        TSFP2 steps per launch; 0 issues the whole solve in one call;
+                 None sizes each request's chunks to about slice_s of device time
+    slice_s      target device time of one chunk (chunk=None)
+    queue_s      estimated device time that may be queued over all requests;
+                 every running request may still keep one chunk queued
     graphs       replay captured graphs for the chunks (vofl_step_graph)
     precision    force every request to this precision (None: the request's)
     keep_results download (u, v) of every request
     """
 
-    def __init__(self, slots=16, budget=None, chunk=64, graphs=True, precision=None,
-                 keep_results=True, workers=4):
+    def __init__(self, slots=16, budget=None, chunk=None, graphs=True, precision=None,
+                 keep_results=True, slice_s=2e-3, queue_s=8e-3):
         import torch
         if not torch.cuda.is_available():
             raise RuntimeError("the server needs a HIP device")
@@ -165,44 +196,32 @@ class Server:
             free, _total = torch.cuda.mem_get_info()
             budget = int(0.9 * free)
         self.admission = Admission(budget, slots)
-        self.chunk = int(chunk)
+        self.chunk = None if chunk is None else int(chunk)
+        self.slice_s = float(slice_s)
+        self.queue_s = float(queue_s)
         self.graphs = bool(graphs)
         self.precision = precision
         self.keep_results = keep_results
-        self.workers = int(workers)
         self.streams = [torch.cuda.Stream(device=self.dev) for _ in range(slots)]
+        self._retired = []          # (plan, nbytes) of finished requests, not yet destroyed
 
-    # -- worker-thread steps ------------------------------------------------
-    def _prepare(self, job: _Job) -> None:
+    def _start(self, job: _Job) -> None:
+        """Build the plan and enqueue the upload of (u0, v0) on the job's stream."""
         torch = self.torch
         r = job.req
-        torch.cuda.set_device(self.dev)
         st = self.streams[job.slot]
+        job.plan = V.Plan(r.shape, r.lo, r.hi, **_plan_kwargs(r, job.precision))
+        dt = torch.float32 if job.precision == "fp32" else torch.float64
+        v0 = np.zeros(r.shape) if r.v0 is None else r.v0
+        host = torch.empty((2,) + tuple(r.shape), dtype=dt, pin_memory=True)
+        host[0].copy_(torch.from_numpy(np.ascontiguousarray(r.u0, dtype=np.float64)))
+        host[1].copy_(torch.from_numpy(np.ascontiguousarray(v0, dtype=np.float64)))
         with torch.cuda.stream(st):
-            job.plan = V.Plan(r.shape, r.lo, r.hi, **_plan_kwargs(r, job.precision))
-            dt = torch.float32 if job.precision == "fp32" else torch.float64
-            job.u = torch.from_numpy(np.ascontiguousarray(r.u0, dtype=np.float64)).to(self.dev, dt)
-            v0 = np.zeros(r.shape) if r.v0 is None else r.v0
-            job.v = torch.from_numpy(np.ascontiguousarray(v0, dtype=np.float64)).to(self.dev, dt)
-        st.synchronize()
+            dev = torch.empty_like(host, device=self.dev)
+            dev.copy_(host, non_blocking=True)
+        job.host, job.dev = host, dev
+        job.u, job.v = dev[0], dev[1]
 
-    def _finish(self, job: _Job):
-        torch = self.torch
-        torch.cuda.set_device(self.dev)
-        st = self.streams[job.slot]
-        rc = V.vofl_sync_status(job.plan.handle, st.cuda_stream)
-        u = v = None
-        if self.keep_results:
-            with torch.cuda.stream(st):
-                u = job.u.double().cpu().numpy().reshape(job.req.shape)
-                v = job.v.double().cpu().numpy().reshape(job.req.shape)
-        done = time.perf_counter() - self._t0  # the result is with the client
-        job.plan.close()
-        job.plan = job.u = job.v = None
-        st.synchronize()
-        return rc, u, v, done
-
-    # -- main loop ----------------------------------------------------------
     def _launch(self, job: _Job, k: int) -> None:
         st = self.streams[job.slot]
         h = job.plan.handle
@@ -212,8 +231,23 @@ class Server:
             V.vofl_step(h, job.u.data_ptr(), job.v.data_ptr(), k, st.cuda_stream)
         ev = self.torch.cuda.Event()
         ev.record(st)
-        job.events.append(ev)
+        job.events.append((ev, k * job.step_s))
         job.issued += k
+
+    def _download(self, job: _Job) -> None:
+        torch = self.torch
+        st = self.streams[job.slot]
+        if self.keep_results:
+            with torch.cuda.stream(st):
+                job.host.copy_(job.dev, non_blocking=True)
+        job.done_ev = torch.cuda.Event()
+        job.done_ev.record(st)
+
+    def _flush_retired(self) -> None:
+        for plan, nbytes in self._retired:
+            plan.close()
+            self.admission.release_memory(nbytes)
+        self._retired = []
 
     def run(self, requests, realtime=True, poll=2e-4):
         """Serve a trace; returns ({index: Result}, stats). With realtime=False
@@ -223,9 +257,10 @@ class Server:
         free_slots = list(range(adm.slots))[::-1]
         jobs = {}
         results = {}
-        self._t0 = t0 = time.perf_counter()
+        inflight = 0.0                # estimated device seconds queued
+        t0 = time.perf_counter()
         clock = lambda: time.perf_counter() - t0  # noqa: E731
-        with cf.ThreadPoolExecutor(max_workers=self.workers) as pool:
+        try:
             while pending or jobs:
                 progressed = False
                 now = clock()
@@ -241,66 +276,91 @@ class Server:
                         progressed = True
                         continue
                     if not adm.try_admit(nbytes):
-                        break
+                        if not self._retired:
+                            break
+                        self._flush_retired()
+                        if not adm.try_admit(nbytes):
+                            break
                     pending.popleft()
                     job = _Job(r, prec, nbytes, free_slots.pop(), now)
-                    job.future = pool.submit(self._prepare, job)
+                    if self.chunk is None:
+                        job.chunk = max(1, min(256, int(round(self.slice_s / job.step_s))))
+                    else:
+                        job.chunk = self.chunk if self.chunk > 0 else max(r.steps, 1)
                     jobs[r.index] = job
+                    try:
+                        self._start(job)
+                    except Exception as exc:  # plan refused or device error
+                        self._retire(job, results, "error", str(exc), clock(), free_slots, jobs)
+                        continue
+                    job.started = clock()
                     progressed = True
+                # retire finished chunks
+                for job in jobs.values():
+                    while job.events and job.events[0][0].query():
+                        inflight -= job.events.popleft()[1]
+                        progressed = True
+                # issue chunks, least remaining work first, within the queue bound
+                for job in sorted((j for j in jobs.values() if j.state == "running"),
+                                  key=lambda j: j.remaining_s()):
+                    r = job.req
+                    while job.issued < r.steps and len(job.events) < 2 and (
+                            not job.events or inflight + job.chunk * job.step_s <= self.queue_s):
+                        k = min(job.chunk, r.steps - job.issued)
+                        self._launch(job, k)
+                        inflight += k * job.step_s
+                        progressed = True
+                    if job.issued >= r.steps:
+                        self._download(job)   # queued behind the last chunk
+                        job.state = "finishing"
+                        progressed = True
                 for idx in list(jobs):
                     job = jobs[idx]
-                    r = job.req
-                    if job.state == "preparing" and job.future.done():
-                        progressed = True
-                        try:
-                            job.future.result()
-                        except Exception as exc:  # plan refused or device error
-                            self._retire(job, results, "error", str(exc), clock(), free_slots, jobs)
-                            continue
-                        job.state = "running"
-                        job.started = clock()
-                    if job.state == "running":
-                        while job.events and job.events[0].query():
-                            job.events.popleft()
-                            progressed = True
-                        step = self.chunk if self.chunk > 0 else r.steps
-                        while job.issued < r.steps and len(job.events) < 2:
-                            self._launch(job, min(step, r.steps - job.issued))
-                            progressed = True
-                        if job.issued >= r.steps and not job.events:
-                            job.state = "finishing"
-                            job.future = pool.submit(self._finish, job)
-                            progressed = True
-                    if job.state == "finishing" and job.future.done():
-                        progressed = True
-                        try:
-                            rc, u, v, done = job.future.result()
-                        except Exception as exc:
-                            self._retire(job, results, "error", str(exc), clock(), free_slots, jobs)
-                            continue
-                        status = "ok" if rc == V.VOFL_OK else ("unstable" if rc == V.VOFL_ERR_UNSTABLE else "error")
+                    if job.state == "finishing" and job.done_ev.query():
+                        while job.events:  # chunks that ended since the scan above
+                            inflight -= job.events.popleft()[1]
+                        rc = V.vofl_sync_status(job.plan.handle, self.streams[job.slot].cuda_stream)
+                        status = ("ok" if rc == V.VOFL_OK else
+                                  "unstable" if rc == V.VOFL_ERR_UNSTABLE else "error")
                         res = self._retire(job, results, status, "" if rc == 0 else "non-finite values",
-                                           done, free_slots, jobs)
-                        res.u, res.v = u, v
+                                           clock(), free_slots, jobs)
+                        if self.keep_results:
+                            res.u = job.host[0].double().numpy().copy()
+                            res.v = job.host[1].double().numpy().copy()
+                        job.host = None
+                        progressed = True
                 if not progressed:
                     if pending and not jobs and realtime and pending[0].arrival > clock():
                         time.sleep(min(pending[0].arrival - clock(), 0.01))
                     else:
                         time.sleep(poll)
+        finally:
+            self.torch.cuda.synchronize()
+            for job in list(jobs.values()):
+                if job.plan is not None:
+                    self._retired.append((job.plan, job.nbytes))
+                    job.plan = None
+            self._flush_retired()
         stats = summarize(results.values(), requests)
         stats.update(peak_active=adm.peak_active, peak_bytes=adm.peak_used, budget=adm.budget,
-                     slots=adm.slots, chunk=self.chunk, graphs=self.graphs)
+                     slots=adm.slots, chunk=self.chunk, slice_s=self.slice_s, queue_s=self.queue_s,
+                     graphs=self.graphs)
         return results, stats
 
     def _retire(self, job, results, status, msg, now, free_slots, jobs):
+        """Record the result and free the slot; the plan's memory is released
+        when the plan is destroyed (_flush_retired)."""
         r = job.req
-        if job.plan is not None:
-            job.plan.close()
-            job.plan = job.u = job.v = None
         res = Result(r.index, status, msg, job.precision, r.arrival, admitted=job.admitted,
                      started=job.started, finished=now)
         results[r.index] = res
-        self.admission.release(job.nbytes)
+        if job.plan is not None:
+            self._retired.append((job.plan, job.nbytes))
+            job.plan = None
+        else:
+            self.admission.release_memory(job.nbytes)
+        job.u = job.v = job.dev = None
+        self.admission.release_slot()
         free_slots.append(job.slot)
         del jobs[r.index]
         return res

@@ -59,6 +59,21 @@ def test_mix_equals_alone_and_oracle():
         assert e <= (TOL_FP32 if prec == "fp32" else TOL_FP64)
 
 
+def test_time_sliced_mix_equals_alone():
+    """Default server (chunks sized to about 2 ms of device time, least
+    remaining work issued first) against the same requests one at a time."""
+    S = _serve()
+    reqs = _trace(10, seed_offset=3, step_scale=0.05)
+    say(f"serve time-sliced mix: {len(reqs)} requests")
+    mix, stats = S.Server(slots=8).run(reqs, realtime=True)
+    say(f"  stats: {stats}")
+    alone, _ = S.Server(slots=1).run(reqs, realtime=False)
+    for r in reqs:
+        assert mix[r.index].status == "ok"
+        assert np.array_equal(mix[r.index].u, alone[r.index].u), f"request {r.index}"
+        assert np.array_equal(mix[r.index].v, alone[r.index].v), f"request {r.index}"
+
+
 def test_budget_bounds_concurrency_and_rejects_oversize():
     S = _serve()
     reqs = _trace(8, seed_offset=1)
