@@ -477,16 +477,27 @@ __device__ __forceinline__ int c2r_nslots(int mode, int M) {
     }
 }
 
-template <typename T, int N, int E, int W, int MODE, int WPE>
+// PD: slot pairs kept in flight (loaded into registers PD transforms ahead).
+// PAIRED: each stored row is loaded once. Pencil positions t and TP - t hold
+// each other's mirror rows (N - (t + TP e) = (TP - t) + TP (E-1-e)), so they
+// are placed in the same wavefront, W lanes apart, and swap their loaded
+// rows with lane shuffles; t = 0 and t = TP/2 are their own mirrors.
+template <typename T, int N, int E, int W, int MODE, int WPE, int PD = 1, bool PAIRED = false>
 __global__ __launch_bounds__(W*(N / E)) __attribute__((amdgpu_waves_per_eu(WPE)))
 void k_c2r0(C2RArgs<T> a) {
     static_assert(MODE >= 0 && MODE <= 3, "mode");
     constexpr int TP = N / E;
+    static_assert(!PAIRED || (E % 2 == 0 && TP >= 2 && W <= 32 && (64 / W) % 2 == 0 && (TP * W) % 64 == 0),
+                  "paired layout needs pencil-position pairs inside a wavefront");
+    constexpr int NL = PAIRED ? E / 2 + 1 : E;  // rows loaded per slot and thread
     __shared__ cpx<T> lds_fft[N * W];
     __shared__ cpx<T> tw_s[N];
     stage_twiddles<T, N>(tw_s, a.tw);
-    const int c = threadIdx.x % W;
-    const int t = threadIdx.x / W;
+    constexpr int TW = (W <= 64) ? 64 / W : 1;  // pencil positions per wavefront
+    const int lane = threadIdx.x % 64, jw = lane / W;
+    const int pr = int(threadIdx.x / 64) * (TW / 2) + jw / 2;  // PAIRED: pair index
+    const int c = PAIRED ? lane % W : threadIdx.x % W;
+    const int t = PAIRED ? ((jw % 2 == 0) ? pr : (pr == 0 ? TP / 2 : TP - pr)) : threadIdx.x / W;
     const int col = blockIdx.x * W + c;
     const bool active = col < a.inner;
     const int colc = active ? col : 0;
@@ -502,41 +513,92 @@ void k_c2r0(C2RArgs<T> a) {
     // time); the next pair is loaded while the current one is transformed.
     // Per-lane 32-bit byte offsets (a half field is below 4 GiB, checked by
     // the plan); the slot base is uniform.
-    unsigned roff[E];
-#pragma unroll
-    for (int e = 0; e < E; ++e) {
+    unsigned roff[NL];
+    auto row_off = [&](int e) __attribute__((always_inline)) -> unsigned {
+        if constexpr (PAIRED) {
+            // rows t + TP e for e < E/2, and the Nyquist row (used by t = 0
+            // only; the other positions load the same cached row and drop it)
+            const int r = (e == E / 2) ? N / 2 : t + TP * e;
+            return (unsigned(r) * unsigned(a.inner) + unsigned(colc)) * unsigned(sizeof(cpx<T>));
+        }
         const int k = t + TP * e;
         const int r = (k <= N / 2) ? k : N - k;
-        roff[e] = (unsigned(r) * unsigned(a.inner) + unsigned(colc)) * unsigned(sizeof(cpx<T>));
-    }
-    cpx<T> p1[E], p2[E];
-    auto load_pair = [&](int tr) __attribute__((always_inline)) {
-        const int s1 = 2 * tr, s2 = 2 * tr + 1;
-        const bool two = s2 < nS;
-        const unsigned bytes = unsigned(a.H * (long long)sizeof(cpx<T>));
-        const auto r1 = make_rsrc(ibase + (long long)s1 * a.H, bytes);
-        const auto r2 = make_rsrc(ibase + (long long)(two ? s2 : s1) * a.H, bytes);
+        return (unsigned(r) * unsigned(a.inner) + unsigned(colc)) * unsigned(sizeof(cpx<T>));
+    };
 #pragma unroll
-        for (int e = 0; e < E; ++e) {
-            p1[e] = buffer_load_cpx<T>(r1, roff[e]);
-            p2[e] = two ? buffer_load_cpx<T>(r2, roff[e]) : cpx<T>{T(0), T(0)};
+    for (int e = 0; e < NL; ++e) roff[e] = row_off(e);
+    cpx<T> p1[PD][E], p2[PD][E];
+    // Loads of pair tr into (q1, q2). A pair past the last one reads through
+    // an empty buffer descriptor (zeros, no memory traffic), and a lone last
+    // slot is loaded twice and masked in build(), so that no branch depends
+    // on the pair index and the compiler can keep PD pairs in flight.
+    auto load_pair = [&](int tr, cpx<T> (&q1)[E], cpx<T> (&q2)[E]) __attribute__((always_inline)) {
+        const bool live = tr < nT;
+        const int s1 = live ? 2 * tr : 0;
+        const int s2 = live ? min(2 * tr + 1, nS - 1) : 0;
+        const unsigned bytes = live ? unsigned(a.H * (long long)sizeof(cpx<T>)) : 0u;
+        const auto r1 = make_rsrc(ibase + (long long)s1 * a.H, bytes);
+        const auto r2 = make_rsrc(ibase + (long long)s2 * a.H, bytes);
+#pragma unroll
+        for (int e = 0; e < NL; ++e) {
+            q1[e] = buffer_load_cpx<T>(r1, roff[e]);
+            q2[e] = buffer_load_cpx<T>(r2, roff[e]);
         }
     };
-    // Y = a + i b with a, b the Hermitian extensions along axis 0
-    auto build = [&](cpx<T> (&y)[E]) __attribute__((always_inline)) {
+    auto shfl = [&](cpx<T> v) __attribute__((always_inline)) -> cpx<T> {
+        return {__shfl_xor(v.x, W), __shfl_xor(v.y, W)};
+    };
+    // Y = a + i b with a, b the Hermitian extensions along axis 0 (selects,
+    // no branches); two = false when the pair has a single slot
+    auto build = [&](cpx<T> (&y)[E], const cpx<T> (&q1)[E], const cpx<T> (&q2)[E], bool two)
+        __attribute__((always_inline)) {
+        if constexpr (PAIRED) {
+            cpx<T> m1[E / 2], m2[E / 2];  // the partner position's loaded rows
+#pragma unroll
+            for (int e = 0; e < E / 2; ++e) {
+                m1[e] = shfl(q1[e]);
+                m2[e] = shfl(q2[e]);
+            }
+            const bool t0 = t == 0, th = t == TP / 2;
+#pragma unroll
+            for (int e = 0; e < E; ++e) {
+                cpx<T> pa, pb;
+                bool lo, edge = false;
+                if (e < E / 2) {
+                    pa = q1[e];
+                    pb = q2[e];
+                    lo = true;
+                    edge = t0 && e == 0;
+                } else if (e == E / 2) {
+                    const cpx<T> o1 = th ? q1[E / 2 - 1] : m1[E / 2 - 1];
+                    const cpx<T> o2 = th ? q2[E / 2 - 1] : m2[E / 2 - 1];
+                    pa = t0 ? q1[E / 2] : o1;
+                    pb = t0 ? q2[E / 2] : o2;
+                    lo = t0;
+                    edge = t0;
+                } else {
+                    const cpx<T> o1 = th ? q1[E - 1 - e] : m1[E - 1 - e];
+                    const cpx<T> o2 = th ? q2[E - 1 - e] : m2[E - 1 - e];
+                    pa = t0 ? q1[E - e] : o1;
+                    pb = t0 ? q2[E - e] : o2;
+                    lo = false;
+                }
+                const T ax = pa.x, ay = edge ? T(0) : pa.y;
+                const T bx = two ? pb.x : T(0);
+                const T by = (two && !edge) ? pb.y : T(0);
+                y[e] = {lo ? ax - by : ax + by, lo ? ay + bx : bx - ay};
+            }
+            return;
+        }
 #pragma unroll
         for (int e = 0; e < E; ++e) {
             const int k = t + TP * e;
-            cpx<T> pa = p1[e], pb = p2[e];
-            if (k <= N / 2) {
-                if (k == 0 || k == N / 2) {
-                    pa.y = T(0);
-                    pb.y = T(0);
-                }
-                y[e] = {pa.x - pb.y, pa.y + pb.x};
-            } else {
-                y[e] = {pa.x + pb.y, pb.x - pa.y};
-            }
+            const bool lo = k <= N / 2;
+            const bool edge = (k == 0) || (k == N / 2);
+            const T ax = q1[e].x, ay = edge ? T(0) : q1[e].y;
+            const T bx = two ? q2[e].x : T(0);
+            const T by = (two && !edge) ? q2[e].y : T(0);
+            y[e] = {lo ? ax - by : ax + by, lo ? ay + bx : bx - ay};
         }
     };
 
@@ -576,10 +638,8 @@ void k_c2r0(C2RArgs<T> a) {
         }
     }
 
-    load_pair(0);
-    for (int tr = 0; tr < nT; ++tr) {
-        build(y);
-        if (tr + 1 < nT) load_pair(tr + 1);  // in flight during the transform
+    // transform tr of the pair held in y: inverse axis-0 FFT and accumulation
+    auto transform = [&](int tr) __attribute__((always_inline)) {
         fft_pencil<T, N, E, +1>(y, t, lds, tw_s);
         if constexpr (MODE == C2R_APPLY) {
 #pragma unroll
@@ -615,6 +675,29 @@ void k_c2r0(C2RArgs<T> a) {
                     }
                 }
             }
+        }
+    };
+
+    // software pipeline: PD pairs in flight; buffer d holds the pairs tr = d
+    // (mod PD). The pair count is padded to a multiple of PD with empty pairs
+    // (zero data: they add nothing to the sums).
+    const int nTp = ((nT + PD - 1) / PD) * PD;
+    // (scheduling barriers keep each pair's loads together, in issue order,
+    // so that the in-order load counter can wait for one pair at a time)
+#pragma unroll
+    for (int d = 0; d < PD; ++d) {
+        load_pair(d, p1[d], p2[d]);
+        __builtin_amdgcn_sched_barrier(0);
+    }
+    for (int base = 0; base < nTp; base += PD) {
+#pragma unroll
+        for (int d = 0; d < PD; ++d) {
+            const int tr = base + d;
+            build(y, p1[d], p2[d], 2 * tr + 1 < nS);
+            __builtin_amdgcn_sched_barrier(0);
+            load_pair(tr + PD, p1[d], p2[d]);  // in flight during the next transforms
+            __builtin_amdgcn_sched_barrier(0);
+            transform(tr);
         }
     }
 

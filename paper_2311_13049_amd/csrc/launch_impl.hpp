@@ -135,15 +135,21 @@ hipError_t Launch<T>::r2c0(int N, const R2CArgs<T>& a, int items, hipStream_t s)
     }
 }
 
-template <typename T, int n, int E, int W, int WPE>
+// the paired layout puts positions t and TP - t W lanes apart in a wavefront
+template <int n, int E, int W>
+constexpr bool paired_ok() {
+    return E % 2 == 0 && n / E >= 2 && W <= 32 && (64 / W) % 2 == 0 && ((n / E) * W) % 64 == 0;
+}
+
+template <typename T, int n, int E, int W, int WPE, int PD = 1, bool PAIRED = false>
 hipError_t c2r0_mode(const C2RArgs<T>& a, int items, hipStream_t s) {
     const dim3 block(W * (n / E));
     const dim3 grid((a.inner + W - 1) / W, items);
     switch (a.mode) {
-        case C2R_APPLY: k_c2r0<T, n, E, W, C2R_APPLY, WPE><<<grid, block, 0, s>>>(a); break;
-        case C2R_KICK: k_c2r0<T, n, E, W, C2R_KICK, WPE><<<grid, block, 0, s>>>(a); break;
-        case C2R_EXPORT: k_c2r0<T, n, E, W, C2R_EXPORT, WPE><<<grid, block, 0, s>>>(a); break;
-        case C2R_KICK_GENERIC: k_c2r0<T, n, E, W, C2R_KICK_GENERIC, WPE><<<grid, block, 0, s>>>(a); break;
+        case C2R_APPLY: k_c2r0<T, n, E, W, C2R_APPLY, WPE, PD, PAIRED><<<grid, block, 0, s>>>(a); break;
+        case C2R_KICK: k_c2r0<T, n, E, W, C2R_KICK, WPE, PD, PAIRED><<<grid, block, 0, s>>>(a); break;
+        case C2R_EXPORT: k_c2r0<T, n, E, W, C2R_EXPORT, WPE, 1, PAIRED><<<grid, block, 0, s>>>(a); break;
+        case C2R_KICK_GENERIC: k_c2r0<T, n, E, W, C2R_KICK_GENERIC, WPE, PD, PAIRED><<<grid, block, 0, s>>>(a); break;
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
@@ -163,10 +169,12 @@ hipError_t c2r0w_mode(const C2RArgs<T>& a, int items, hipStream_t s) {
 }
 
 // variants of the axis-0 kernel: 0 -> k_c2r0 (W columns, direct register
-// loads); 2 -> k_c2r0 with W/2 columns; 5 -> k_c2r0w (wave-local
-// transforms, E = 8, 4 waves); 6 -> k_c2r0w with 8 waves. Variants 5 and 6
-// exist for FP32 lengths without a factor 3 and not for the export mode;
-// elsewhere they fall back to variant 0.
+// loads of rows min(k, N-k)); 2 -> k_c2r0 with W/2 columns; 11, 12 ->
+// k_c2r0 loading each stored row once (paired layout), with 1 and 2 slot
+// pairs in flight; 5 -> k_c2r0w (wave-local transforms, E = 8, 4 waves);
+// 6 -> k_c2r0w with 8 waves. A variant that does not exist for a length
+// (see c2r_variant_exists) falls back to variant 0; variants 5 and 6 also
+// fall back to 0 in the export mode.
 template <typename T>
 hipError_t Launch<T>::c2r0(int N, const C2RArgs<T>& a, int items, hipStream_t s, int variant) {
     switch (N) {
@@ -175,6 +183,11 @@ hipError_t Launch<T>::c2r0(int N, const C2RArgs<T>& a, int items, hipStream_t s,
         constexpr int W = c2r_width<T, n>(), E = e_c2r0(n);                             \
         constexpr int W2 = (W >= 8) ? W / 2 : W;                                        \
         if (variant == 2 && W2 != W) return c2r0_mode<T, n, E, W2, 1>(a, items, s);     \
+        if constexpr (paired_ok<n, E, W>()) {                                           \
+            if (variant == 11) return c2r0_mode<T, n, E, W, 1, 1, true>(a, items, s);   \
+            if constexpr (sizeof(T) == 4 && E <= 8)                                       \
+                if (variant == 12) return c2r0_mode<T, n, E, W, 1, 2, true>(a, items, s); \
+        }                                                                               \
         if constexpr (C2RW<T, n, 8, 4>::ok && sizeof(T) == 4)                           \
             if (variant == 5 && a.mode != C2R_EXPORT) return c2r0w_mode<T, n, 8, 4>(a, items, s); \
         if constexpr (C2RW<T, n, 8, 8>::ok && sizeof(T) == 4)                           \
@@ -192,9 +205,11 @@ bool Launch<T>::c2r_variant_exists(int N, int variant) {
     switch (N) {
 #define C_(n)                                                                           \
     case n: {                                                                           \
-        constexpr int W = c2r_width<T, n>();                                            \
+        constexpr int W = c2r_width<T, n>(), E = e_c2r0(n);                             \
         if (variant == 0) return true;                                                  \
         if (variant == 2) return W >= 8;                                                \
+        if (variant == 11) return paired_ok<n, E, W>();                                 \
+        if (variant == 12) return paired_ok<n, E, W>() && sizeof(T) == 4 && E <= 8;     \
         if (variant == 5) return C2RW<T, n, 8, 4>::ok && sizeof(T) == 4;                \
         if (variant == 6) return C2RW<T, n, 8, 8>::ok && sizeof(T) == 4;                \
         return false;                                                                   \

@@ -668,7 +668,7 @@ int autotune(vofl_plan_s* p, int steps) {
     if (e == hipSuccess) e = hipEventCreate(&e1);
     int rc = (e == hipSuccess) ? VOFL_OK : hip_fail(e, "autotune setup");
     std::vector<int> c2r, mid;
-    for (int c : {0, 2, 5, 6})
+    for (int c : {0, 2, 5, 6, 11, 12})
         if (Launch<T>::c2r_variant_exists(g.n[0], c)) c2r.push_back(c);
     mid.push_back(0);
     if (g.ndim == 3 && Launch<T>::mid_tile(g.n[1], 1) != Launch<T>::mid_tile(g.n[1], 0)) mid.push_back(1);
@@ -807,6 +807,13 @@ int vofl_plan(const vofl_desc* d, void* stream, vofl_plan_t* out) {
         p->hi[i] = d->hi[i];
     }
     p->sc_host = sc;
+    // default axis-0 kernel: the paired layout (each stored row loaded once)
+    // where the length allows it
+    if (g.ndim >= 2) {
+        const bool paired = (d->precision == VOFL_FP32) ? Launch<float>::c2r_variant_exists(g.n[0], 11)
+                                                        : Launch<double>::c2r_variant_exists(g.n[0], 11);
+        p->c2r_variant = paired ? 11 : 0;
+    }
     if (const char* ev = std::getenv("VOFL_C2R_VARIANT")) p->c2r_variant = std::atoi(ev);
     if (const char* ev = std::getenv("VOFL_MID_VARIANT")) p->mid_variant = std::atoi(ev);
     rc = (d->precision == VOFL_FP32) ? upload_tables<float>(p, delta, A, B)

@@ -265,3 +265,41 @@ def test_unstable_flag_table4_entry():
     p.step(u, v, 128)
     assert p.sync_status() == V.VOFL_ERR_UNSTABLE
     assert p.sync_status() == 0  # flag cleared by the read
+
+
+# --------------------------------------------------------------------------
+# every selectable axis-0 kernel variant (the autotuner may pick any of them)
+# --------------------------------------------------------------------------
+
+VARIANT_CASES = [
+    ((64, 8, 48), (-4.0, -1.0, -3.0), (4.0, 1.0, 3.0)),   # 3D, 384 columns
+    ((128, 8), (-8.0, -1.0), (8.0, 1.0)),                 # 2D, fewer columns than a tile
+    ((256, 8, 16), (-16.0, -1.0, -2.0), (16.0, 1.0, 2.0)),  # axis 0 of the 256^3 workload
+]
+
+
+@pytest.mark.parametrize("variant", [0, 2, 5, 6, 11, 12])
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+@pytest.mark.parametrize("case", range(len(VARIANT_CASES)))
+def test_axis0_variants_apply_and_step(case, precision, variant):
+    import os
+    shape, lo, hi = VARIANT_CASES[case]
+    Q, gamma = _grf_gamma(shape, lo, hi, 60 + case)
+    u0 = gaussian_pulse(shape, lo, hi, [0.3] * len(shape))
+    say(f"axis-0 variant {variant} {shape} {precision}")
+    os.environ["VOFL_C2R_VARIANT"] = str(variant)
+    try:
+        p = _plan(shape, lo, hi, precision, Q=Q, M=6, dt=2e-3, max_batch=2)
+    finally:
+        del os.environ["VOFL_C2R_VARIANT"]
+    assert p.info()["c2r_variant"] == variant
+    u_in = as_seen(u0, precision)
+    out = host(p.apply(1, dev(u0, precision))).reshape(shape)
+    ref = O.mterm_apply(u_in, 1.0 + gamma, lo, hi, 6)
+    assert rel_l2(out, ref) <= tol(precision), rel_l2(out, ref)
+    u, v = dev(u0, precision), dev(np.zeros(shape), precision)
+    p.step(u, v, 4)
+    assert p.sync_status() == 0
+    ru, rv = O.tsfp2_seismic(u_in, np.zeros(shape), gamma, 1.0, 1.0, lo, hi, 6, 2e-3, 4)
+    assert rel_l2(host(u), ru) <= tol(precision), rel_l2(host(u), ru)
+    assert rel_l2(host(v), rv) <= tol(precision) * 10, rel_l2(host(v), rv)
