@@ -284,4 +284,76 @@ __device__ __forceinline__ void fft_pencil(cpx<T> (&v)[E], const int t, const Ld
     fft_stages<T, N, E, DIR, 1, Lds, WAVE>(v, t, lds, tw);
 }
 
+// Two-buffer ("ping-pong") form for kernels that run many transforms in a
+// row: exchange s writes and reads buffer s mod 2, so only the barrier
+// between an exchange's writes and its reads is needed. A wave that starts
+// the next exchange writes the other buffer, which every wave has finished
+// reading (it read it before the barrier it just passed). With an odd number
+// of exchanges the transform ends with one barrier, so that the next
+// transform's first exchange (buffer 0) cannot overwrite the last one's
+// (also buffer 0) under a slower wave.
+template <typename T, int N, int E, int DIR, int NS, int S, class Lds, bool TAIL = true>
+__device__ __forceinline__ void fft_stages_pp(cpx<T> (&v)[E], const int t, const Lds& l0, const Lds& l1,
+                                              const cpx<T>* __restrict__ tw) {
+    constexpr int R = pick_radix(N / NS, E);
+    static_assert(R > 1, "length not supported by the radix set");
+    constexpr int TP = N / E;
+    constexpr int Q = E / R;
+    constexpr bool LAST = (NS * R == N);
+    const Lds& lds = (S % 2 == 0) ? l0 : l1;
+    cpx<T> out[E];
+#pragma unroll
+    for (int q = 0; q < Q; ++q) {
+        const int b = t + q * TP;
+        cpx<T> w[R];
+#pragma unroll
+        for (int r = 0; r < R; ++r) w[r] = v[q + r * Q];
+        if constexpr (NS > 1) {
+            const int k = b % NS;
+#pragma unroll
+            for (int r = 1; r < R; ++r) w[r] = twmul<DIR>(w[r], tw[k * r * (N / (NS * R))]);
+        }
+        dft<R, DIR>(w);
+        if constexpr (LAST) {
+#pragma unroll
+            for (int r = 0; r < R; ++r) out[q + r * Q] = w[r];
+        } else {
+            const int k = b % NS;
+            const int base = (b / NS) * NS * R + k;
+#pragma unroll
+            for (int r = 0; r < R; ++r) lds[base + r * NS] = w[r];
+        }
+    }
+    if constexpr (LAST) {
+#pragma unroll
+        for (int e = 0; e < E; ++e) v[e] = out[e];
+        if constexpr (TAIL && S % 2 == 1) __syncthreads();  // odd number of exchanges (S of them)
+    } else {
+        __syncthreads();
+#pragma unroll
+        for (int e = 0; e < E; ++e) v[e] = lds[t + e * TP];
+        fft_stages_pp<T, N, E, DIR, NS * R, S + 1, Lds, TAIL>(v, t, l0, l1, tw);
+    }
+}
+
+// Length-N transform with two LDS buffers (see fft_stages_pp); every thread
+// of the workgroup must call it, and between two calls the buffers may be
+// used for nothing else.
+template <typename T, int N, int E, int DIR, class Lds>
+__device__ __forceinline__ void fft_pencil_pp(cpx<T> (&v)[E], const int t, const Lds& l0, const Lds& l1,
+                                              const cpx<T>* __restrict__ tw) {
+    static_assert(N % E == 0, "E must divide N");
+    static_assert(num_stages(N, E) > 0, "length not supported");
+    fft_stages_pp<T, N, E, DIR, 1, 0, Lds>(v, t, l0, l1, tw);
+}
+
+// Single transform per workgroup with one exchange: one LDS buffer and one
+// barrier (nothing reuses the buffer afterwards).
+template <typename T, int N, int E, int DIR, class Lds>
+__device__ __forceinline__ void fft_pencil_once(cpx<T> (&v)[E], const int t, const Lds& l0,
+                                                const cpx<T>* __restrict__ tw) {
+    static_assert(num_stages(N, E) == 2, "one exchange only");
+    fft_stages_pp<T, N, E, DIR, 1, 0, Lds, false>(v, t, l0, l0, tw);
+}
+
 }  // namespace vofl

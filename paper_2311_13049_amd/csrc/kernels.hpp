@@ -27,6 +27,7 @@
 #pragma once
 
 #include "fft_engine.hpp"
+#include <type_traits>
 
 namespace vofl {
 
@@ -359,7 +360,8 @@ __global__ __launch_bounds__(W*(N / E)) void k_mid(MidArgs<T> a) {
     cpx<T> v[E];
 #pragma unroll
     for (int e = 0; e < E; ++e) v[e] = base[(long long)(t + TP * e) * a.n2];
-    fft_pencil<T, N, E, DIR>(v, t, lds, tw_s);
+    if constexpr (num_stages(N, E) == 2) fft_pencil_once<T, N, E, DIR>(v, t, lds, tw_s);
+    else fft_pencil<T, N, E, DIR>(v, t, lds, tw_s);
     if (active) {
 #pragma unroll
         for (int e = 0; e < E; ++e) base[(long long)(t + TP * e) * a.n2] = v[e];
@@ -490,7 +492,9 @@ void k_c2r0(C2RArgs<T> a) {
     static_assert(!PAIRED || (E % 2 == 0 && TP >= 2 && W <= 32 && (64 / W) % 2 == 0 && (TP * W) % 64 == 0),
                   "paired layout needs pencil-position pairs inside a wavefront");
     constexpr int NL = PAIRED ? E / 2 + 1 : E;  // rows loaded per slot and thread
+    // the paired variants also use a second FFT buffer (one barrier per exchange)
     __shared__ cpx<T> lds_fft[N * W];
+    __shared__ cpx<T> lds_fft2[PAIRED ? N * W : 1];
     __shared__ cpx<T> tw_s[N];
     stage_twiddles<T, N>(tw_s, a.tw);
     constexpr int TW = (W <= 64) ? 64 / W : 1;  // pencil positions per wavefront
@@ -503,6 +507,11 @@ void k_c2r0(C2RArgs<T> a) {
     const int colc = active ? col : 0;
     const int item = blockIdx.y;
     const LdsColumn<T, W> lds{lds_fft + c};
+    const LdsColumn<T, W> lds2{lds_fft2 + (PAIRED ? c : 0)};
+    auto fft = [&](cpx<T> (&x)[E], auto dir) __attribute__((always_inline)) {
+        if constexpr (PAIRED) fft_pencil_pp<T, N, E, decltype(dir)::value, LdsColumn<T, W>>(x, t, lds, lds2, tw_s);
+        else fft_pencil<T, N, E, decltype(dir)::value>(x, t, lds, tw_s);
+    };
     const cpx<T>* ibase = a.in + (long long)item * a.istride;  // uniform
     const int nT = c2r_transforms(MODE, a.M);
     const int nS = c2r_nslots(MODE, a.M);
@@ -640,7 +649,7 @@ void k_c2r0(C2RArgs<T> a) {
 
     // transform tr of the pair held in y: inverse axis-0 FFT and accumulation
     auto transform = [&](int tr) __attribute__((always_inline)) {
-        fft_pencil<T, N, E, +1>(y, t, lds, tw_s);
+        fft(y, std::integral_constant<int, +1>{});
         if constexpr (MODE == C2R_APPLY) {
 #pragma unroll
             for (int e = 0; e < E; ++e) {
@@ -732,7 +741,7 @@ void k_c2r0(C2RArgs<T> a) {
         z[e] = {dv, T(0)};
     }
     if (bad && active) a.flag[0] = 1;
-    fft_pencil<T, N, E, -1>(z, t, lds, tw_s);
+    fft(z, std::integral_constant<int, -1>{});
     if (active) {
         cpx<T>* dst = a.dv_out + (long long)item * a.istride + colc;
 #pragma unroll
