@@ -336,6 +336,102 @@ __device__ __forceinline__ void fft_stages_pp(cpx<T> (&v)[E], const int t, const
     }
 }
 
+// Twiddles of one thread, held in registers for kernels that run many
+// transforms: for every stage after the first, its Q butterflies' R-1
+// twiddles, in stage order. tw_count gives the number of values.
+constexpr int tw_count(int N, int E) {
+    int c = 0, ns = 1;
+    while (ns < N) {
+        const int r = pick_radix(N / ns, E);
+        if (r <= 1) return -1;
+        if (ns > 1) c += (E / r) * (r - 1);
+        ns *= r;
+    }
+    return c;
+}
+
+template <typename T, int N, int E, int NS, int OFF, int C>
+__device__ __forceinline__ void load_twiddles_at(cpx<T> (&w)[C], const int t, const cpx<T>* __restrict__ tw) {
+    if constexpr (NS < N) {
+        constexpr int R = pick_radix(N / NS, E);
+        constexpr int TP = N / E, Q = E / R;
+        if constexpr (NS > 1) {
+#pragma unroll
+            for (int q = 0; q < Q; ++q) {
+                const int k = (t + q * TP) % NS;
+#pragma unroll
+                for (int r = 1; r < R; ++r) w[OFF + q * (R - 1) + r - 1] = tw[k * r * (N / (NS * R))];
+            }
+            load_twiddles_at<T, N, E, NS * R, OFF + Q * (R - 1), C>(w, t, tw);
+        } else {
+            load_twiddles_at<T, N, E, NS * R, OFF, C>(w, t, tw);
+        }
+    }
+}
+
+// Fill w with thread t's twiddles (tw: the length-N table, e.g. in LDS).
+template <typename T, int N, int E, int C>
+__device__ __forceinline__ void load_twiddles(cpx<T> (&w)[C], const int t, const cpx<T>* __restrict__ tw) {
+    static_assert(C == tw_count(N, E), "twiddle register count");
+    load_twiddles_at<T, N, E, 1, 0, C>(w, t, tw);
+}
+
+// Stockham stages as in fft_stages_pp, with the twiddles taken from
+// registers (w, filled by load_twiddles) instead of a table.
+template <typename T, int N, int E, int DIR, int NS, int S, int OFF, class Lds, int C>
+__device__ __forceinline__ void fft_stages_ppr(cpx<T> (&v)[E], const int t, const Lds& l0, const Lds& l1,
+                                               const cpx<T> (&w)[C]) {
+    constexpr int R = pick_radix(N / NS, E);
+    static_assert(R > 1, "length not supported by the radix set");
+    constexpr int TP = N / E;
+    constexpr int Q = E / R;
+    constexpr bool LAST = (NS * R == N);
+    const Lds& lds = (S % 2 == 0) ? l0 : l1;
+    cpx<T> out[E];
+#pragma unroll
+    for (int q = 0; q < Q; ++q) {
+        const int b = t + q * TP;
+        cpx<T> x[R];
+#pragma unroll
+        for (int r = 0; r < R; ++r) x[r] = v[q + r * Q];
+        if constexpr (NS > 1) {
+#pragma unroll
+            for (int r = 1; r < R; ++r) x[r] = twmul<DIR>(x[r], w[OFF + q * (R - 1) + r - 1]);
+        }
+        dft<R, DIR>(x);
+        if constexpr (LAST) {
+#pragma unroll
+            for (int r = 0; r < R; ++r) out[q + r * Q] = x[r];
+        } else {
+            const int k = b % NS;
+            const int base = (b / NS) * NS * R + k;
+#pragma unroll
+            for (int r = 0; r < R; ++r) lds[base + r * NS] = x[r];
+        }
+    }
+    if constexpr (LAST) {
+#pragma unroll
+        for (int e = 0; e < E; ++e) v[e] = out[e];
+        if constexpr (S % 2 == 1) __syncthreads();  // odd number of exchanges
+    } else {
+        __syncthreads();
+#pragma unroll
+        for (int e = 0; e < E; ++e) v[e] = lds[t + e * TP];
+        constexpr int NOFF = (NS > 1) ? OFF + Q * (R - 1) : OFF;
+        fft_stages_ppr<T, N, E, DIR, NS * R, S + 1, NOFF, Lds, C>(v, t, l0, l1, w);
+    }
+}
+
+// Two-buffer transform with register twiddles (see fft_stages_pp for the
+// synchronisation contract).
+template <typename T, int N, int E, int DIR, class Lds, int C>
+__device__ __forceinline__ void fft_pencil_ppr(cpx<T> (&v)[E], const int t, const Lds& l0, const Lds& l1,
+                                               const cpx<T> (&w)[C]) {
+    static_assert(N % E == 0, "E must divide N");
+    static_assert(num_stages(N, E) > 0, "length not supported");
+    fft_stages_ppr<T, N, E, DIR, 1, 0, 0, Lds, C>(v, t, l0, l1, w);
+}
+
 // Length-N transform with two LDS buffers (see fft_stages_pp); every thread
 // of the workgroup must call it, and between two calls the buffers may be
 // used for nothing else.

@@ -508,8 +508,16 @@ void k_c2r0(C2RArgs<T> a) {
     const int item = blockIdx.y;
     const LdsColumn<T, W> lds{lds_fft + c};
     const LdsColumn<T, W> lds2{lds_fft2 + (PAIRED ? c : 0)};
+    // the paired variants with E <= 8 keep this thread's twiddles in
+    // registers for all the transforms of the kernel
+    constexpr bool TWREG = PAIRED && E <= 8 && tw_count(N, E) > 0 && tw_count(N, E) <= 16;
+    constexpr int TWC = TWREG ? tw_count(N, E) : 1;
+    cpx<T> twr[TWC];
+    if constexpr (TWREG) load_twiddles<T, N, E, TWC>(twr, t, tw_s);
     auto fft = [&](cpx<T> (&x)[E], auto dir) __attribute__((always_inline)) {
-        if constexpr (PAIRED) fft_pencil_pp<T, N, E, decltype(dir)::value, LdsColumn<T, W>>(x, t, lds, lds2, tw_s);
+        if constexpr (TWREG)
+            fft_pencil_ppr<T, N, E, decltype(dir)::value, LdsColumn<T, W>, TWC>(x, t, lds, lds2, twr);
+        else if constexpr (PAIRED) fft_pencil_pp<T, N, E, decltype(dir)::value, LdsColumn<T, W>>(x, t, lds, lds2, tw_s);
         else fft_pencil<T, N, E, decltype(dir)::value>(x, t, lds, tw_s);
     };
     const cpx<T>* ibase = a.in + (long long)item * a.istride;  // uniform
@@ -626,7 +634,13 @@ void k_c2r0(C2RArgs<T> a) {
     //  apply:   acc = sum_m delta^m t_m
     //  kick:    acc = (kappa0 - A) t1_0 + (beta0 - B) t2_0 + sum_{m>=1} delta^m (-A t1_m - B t2_m)
     //  generic: acc = -kappa sum_{s=1..M} delta^s t_s, uu = IDFT(u_hat)
+    // FP32 kick (SPLIT): the m >= 1 part is accumulated as S1 = sum delta^m t1_m
+    // and S2 = sum delta^m t2_m (delta^m rounded once) and multiplied by -A,
+    // -B at the end; these sums are small corrections to the m = 0 term, and
+    // the split saves three instructions per point and transform.
+    constexpr bool SPLIT = MODE == C2R_KICK && sizeof(T) == 4;
     T acc[E], cA[E], cB[E];
+    T S1[SPLIT ? E : 1], S2[SPLIT ? E : 1];
     double dm[E];
     cpx<T> y[E];
 #pragma unroll
@@ -635,6 +649,10 @@ void k_c2r0(C2RArgs<T> a) {
         dm[e] = 1.0;
         cA[e] = T(0);
         cB[e] = T(0);
+        if constexpr (SPLIT) {
+            S1[e] = T(0);
+            S2[e] = T(0);
+        }
     }
     if constexpr (MODE == C2R_KICK) {
         const T* Ap = a.A + (long long)item * a.coef_stride + colc;
@@ -657,16 +675,31 @@ void k_c2r0(C2RArgs<T> a) {
                 acc[e] += T(dm[e]) * y[e].x + T(dm[e] * d) * y[e].y;
                 dm[e] *= d * d;
             }
+        } else if constexpr (SPLIT) {
+            if (tr == 0) {
+#pragma unroll
+                for (int e = 0; e < E; ++e) {
+                    acc[e] = T(sc.kappa0 + double(cA[e])) * y[e].x + T(sc.beta0 + double(cB[e])) * y[e].y;
+                    dm[e] = dl[e];
+                }
+            } else {
+#pragma unroll
+                for (int e = 0; e < E; ++e) {
+                    const T w = T(dm[e]);
+                    S1[e] += w * y[e].x;
+                    S2[e] += w * y[e].y;
+                    dm[e] *= dl[e];
+                }
+            }
         } else if constexpr (MODE == C2R_KICK) {
             const double k0c = (tr == 0) ? sc.kappa0 : 0.0;
             const double b0c = (tr == 0) ? sc.beta0 : 0.0;
 #pragma unroll
             for (int e = 0; e < E; ++e) {
-                const double d = dl[e];
                 const T ca = T(k0c + double(cA[e]) * dm[e]);
                 const T cb = T(b0c + double(cB[e]) * dm[e]);
                 acc[e] += ca * y[e].x + cb * y[e].y;
-                dm[e] *= d;
+                dm[e] *= dl[e];
             }
         } else if constexpr (MODE == C2R_KICK_GENERIC) {
 #pragma unroll
@@ -736,6 +769,7 @@ void k_c2r0(C2RArgs<T> a) {
 #pragma unroll
     for (int e = 0; e < E; ++e) {
         T dv = acc[e];
+        if constexpr (SPLIT) dv += cA[e] * S1[e] + cB[e] * S2[e];
         if constexpr (MODE == C2R_KICK_GENERIC) dv += T(sc.lambda) * cB[e] * cB[e] * cB[e];
         bad |= !isfinite(dv);
         z[e] = {dv, T(0)};
