@@ -227,15 +227,100 @@ __device__ __forceinline__ void exchange_sync() {
     }
 }
 
-// One Stockham stage with stride NS (product of the radices done before).
-template <typename T, int N, int E, int DIR, int NS, class Lds, bool WAVE = false>
-__device__ __forceinline__ void fft_stages(cpx<T> (&v)[E], const int t, const Lds& lds,
-                                           const cpx<T>* __restrict__ tw) {
+// Twiddle sources for the stages. TwTable reads the length-N table
+// tw[j] = exp(-2 pi i j/N) (global memory or LDS). TwRegs reads a thread's
+// own twiddles from registers (filled once by load_twiddles), for kernels
+// that run many transforms: for every stage after the first, its Q
+// butterflies' R-1 twiddles, in stage order.
+constexpr int tw_count(int N, int E) {
+    int c = 0, ns = 1;
+    while (ns < N) {
+        const int r = pick_radix(N / ns, E);
+        if (r <= 1) return -1;
+        if (ns > 1) c += (E / r) * (r - 1);
+        ns *= r;
+    }
+    return c;
+}
+// offset of the stage with stride NS in a TwRegs array
+constexpr int tw_offset(int N, int E, int NS) {
+    int c = 0, ns = 1;
+    while (ns < NS) {
+        const int r = pick_radix(N / ns, E);
+        if (ns > 1) c += (E / r) * (r - 1);
+        ns *= r;
+    }
+    return c;
+}
+
+template <typename T>
+struct TwTable {
+    const cpx<T>* __restrict__ tw;
+    template <int N, int E, int NS, int R>
+    __device__ __forceinline__ cpx<T> get(int, int r, int k) const {
+        return tw[k * r * (N / (NS * R))];
+    }
+};
+template <typename T, int C>
+struct TwRegs {
+    const cpx<T> (&w)[C];
+    template <int N, int E, int NS, int R>
+    __device__ __forceinline__ cpx<T> get(int q, int r, int) const {
+        return w[tw_offset(N, E, NS) + q * (R - 1) + r - 1];
+    }
+};
+
+template <typename T, int N, int E, int NS, int C>
+__device__ __forceinline__ void load_twiddles_at(cpx<T> (&w)[C], const int t, const cpx<T>* __restrict__ tw) {
+    if constexpr (NS < N) {
+        constexpr int R = pick_radix(N / NS, E);
+        constexpr int TP = N / E, Q = E / R, OFF = tw_offset(N, E, NS);
+        if constexpr (NS > 1) {
+#pragma unroll
+            for (int q = 0; q < Q; ++q) {
+                const int k = (t + q * TP) % NS;
+#pragma unroll
+                for (int r = 1; r < R; ++r) w[OFF + q * (R - 1) + r - 1] = tw[k * r * (N / (NS * R))];
+            }
+        }
+        load_twiddles_at<T, N, E, NS * R, C>(w, t, tw);
+    }
+}
+
+// Fill w with thread t's twiddles (tw: the length-N table, e.g. in LDS).
+template <typename T, int N, int E, int C>
+__device__ __forceinline__ void load_twiddles(cpx<T> (&w)[C], const int t, const cpx<T>* __restrict__ tw) {
+    static_assert(C == tw_count(N, E), "twiddle register count");
+    load_twiddles_at<T, N, E, 1, C>(w, t, tw);
+}
+
+// Synchronisation of the exchanges (SYNC):
+//  SYNC_BOTH  single LDS buffer, sync between an exchange's writes and reads
+//             and again after the reads (the next stage overwrites it);
+//  SYNC_PP    two buffers ("ping-pong") for kernels that run many transforms
+//             in a row: exchange s uses buffer s mod 2, so only the sync
+//             between writes and reads is needed. A wave that starts the
+//             next exchange writes the other buffer, which every wave has
+//             finished reading (it read it before the sync it just passed).
+//             With an odd number of exchanges the transform ends with one
+//             sync, so that the next transform's first exchange (buffer 0)
+//             cannot overwrite the last one's (also buffer 0) under a slower
+//             wave;
+//  SYNC_ONCE  one transform per workgroup with a single exchange: one
+//             buffer, one sync (nothing reuses the buffer afterwards).
+enum { SYNC_BOTH = 0, SYNC_PP = 1, SYNC_ONCE = 2 };
+
+// One Stockham stage with stride NS (product of the radices done before);
+// S counts the stages done.
+template <typename T, int N, int E, int DIR, int NS, int S, int SYNC, bool WAVE, class Lds, class TW>
+__device__ __forceinline__ void fft_stages(cpx<T> (&v)[E], const int t, const Lds& l0, const Lds& l1,
+                                           const TW& tws) {
     constexpr int R = pick_radix(N / NS, E);
     static_assert(R > 1, "length not supported by the radix set");
     constexpr int TP = N / E;
     constexpr int Q = E / R;  // butterflies per thread in this stage
     constexpr bool LAST = (NS * R == N);
+    const Lds& lds = (SYNC == SYNC_PP && S % 2 == 1) ? l1 : l0;
     cpx<T> out[E];
 #pragma unroll
     for (int q = 0; q < Q; ++q) {
@@ -246,7 +331,7 @@ __device__ __forceinline__ void fft_stages(cpx<T> (&v)[E], const int t, const Ld
         if constexpr (NS > 1) {
             const int k = b % NS;
 #pragma unroll
-            for (int r = 1; r < R; ++r) w[r] = twmul<DIR>(w[r], tw[k * r * (N / (NS * R))]);
+            for (int r = 1; r < R; ++r) w[r] = twmul<DIR>(w[r], tws.template get<N, E, NS, R>(q, r, k));
         }
         dft<R, DIR>(w);
         if constexpr (LAST) {
@@ -262,12 +347,13 @@ __device__ __forceinline__ void fft_stages(cpx<T> (&v)[E], const int t, const Ld
     if constexpr (LAST) {
 #pragma unroll
         for (int e = 0; e < E; ++e) v[e] = out[e];
+        if constexpr (SYNC == SYNC_PP && S % 2 == 1) exchange_sync<WAVE>();  // odd number of exchanges
     } else {
         exchange_sync<WAVE>();
 #pragma unroll
         for (int e = 0; e < E; ++e) v[e] = lds[t + e * TP];
-        exchange_sync<WAVE>();
-        fft_stages<T, N, E, DIR, NS * R, Lds, WAVE>(v, t, lds, tw);
+        if constexpr (SYNC == SYNC_BOTH) exchange_sync<WAVE>();
+        fft_stages<T, N, E, DIR, NS * R, S + 1, SYNC, WAVE, Lds, TW>(v, t, l0, l1, tws);
     }
 }
 
@@ -281,175 +367,38 @@ __device__ __forceinline__ void fft_pencil(cpx<T> (&v)[E], const int t, const Ld
     static_assert(N % E == 0, "E must divide N");
     static_assert(num_stages(N, E) > 0, "length not supported");
     static_assert(!WAVE || (N / E) <= 64, "a wave-synchronised pencil must fit in one wavefront");
-    fft_stages<T, N, E, DIR, 1, Lds, WAVE>(v, t, lds, tw);
+    fft_stages<T, N, E, DIR, 1, 0, SYNC_BOTH, WAVE>(v, t, lds, lds, TwTable<T>{tw});
 }
 
-// Two-buffer ("ping-pong") form for kernels that run many transforms in a
-// row: exchange s writes and reads buffer s mod 2, so only the barrier
-// between an exchange's writes and its reads is needed. A wave that starts
-// the next exchange writes the other buffer, which every wave has finished
-// reading (it read it before the barrier it just passed). With an odd number
-// of exchanges the transform ends with one barrier, so that the next
-// transform's first exchange (buffer 0) cannot overwrite the last one's
-// (also buffer 0) under a slower wave.
-template <typename T, int N, int E, int DIR, int NS, int S, class Lds, bool TAIL = true>
-__device__ __forceinline__ void fft_stages_pp(cpx<T> (&v)[E], const int t, const Lds& l0, const Lds& l1,
-                                              const cpx<T>* __restrict__ tw) {
-    constexpr int R = pick_radix(N / NS, E);
-    static_assert(R > 1, "length not supported by the radix set");
-    constexpr int TP = N / E;
-    constexpr int Q = E / R;
-    constexpr bool LAST = (NS * R == N);
-    const Lds& lds = (S % 2 == 0) ? l0 : l1;
-    cpx<T> out[E];
-#pragma unroll
-    for (int q = 0; q < Q; ++q) {
-        const int b = t + q * TP;
-        cpx<T> w[R];
-#pragma unroll
-        for (int r = 0; r < R; ++r) w[r] = v[q + r * Q];
-        if constexpr (NS > 1) {
-            const int k = b % NS;
-#pragma unroll
-            for (int r = 1; r < R; ++r) w[r] = twmul<DIR>(w[r], tw[k * r * (N / (NS * R))]);
-        }
-        dft<R, DIR>(w);
-        if constexpr (LAST) {
-#pragma unroll
-            for (int r = 0; r < R; ++r) out[q + r * Q] = w[r];
-        } else {
-            const int k = b % NS;
-            const int base = (b / NS) * NS * R + k;
-#pragma unroll
-            for (int r = 0; r < R; ++r) lds[base + r * NS] = w[r];
-        }
-    }
-    if constexpr (LAST) {
-#pragma unroll
-        for (int e = 0; e < E; ++e) v[e] = out[e];
-        if constexpr (TAIL && S % 2 == 1) __syncthreads();  // odd number of exchanges (S of them)
-    } else {
-        __syncthreads();
-#pragma unroll
-        for (int e = 0; e < E; ++e) v[e] = lds[t + e * TP];
-        fft_stages_pp<T, N, E, DIR, NS * R, S + 1, Lds, TAIL>(v, t, l0, l1, tw);
-    }
+// The same with the thread's twiddles in registers (see load_twiddles).
+template <typename T, int N, int E, int DIR, class Lds, bool WAVE, int C>
+__device__ __forceinline__ void fft_pencil_r(cpx<T> (&v)[E], const int t, const Lds& lds, const cpx<T> (&w)[C]) {
+    static_assert(N % E == 0 && num_stages(N, E) > 0, "length not supported");
+    static_assert(!WAVE || (N / E) <= 64, "a wave-synchronised pencil must fit in one wavefront");
+    fft_stages<T, N, E, DIR, 1, 0, SYNC_BOTH, WAVE>(v, t, lds, lds, TwRegs<T, C>{w});
 }
 
-// Twiddles of one thread, held in registers for kernels that run many
-// transforms: for every stage after the first, its Q butterflies' R-1
-// twiddles, in stage order. tw_count gives the number of values.
-constexpr int tw_count(int N, int E) {
-    int c = 0, ns = 1;
-    while (ns < N) {
-        const int r = pick_radix(N / ns, E);
-        if (r <= 1) return -1;
-        if (ns > 1) c += (E / r) * (r - 1);
-        ns *= r;
-    }
-    return c;
-}
-
-template <typename T, int N, int E, int NS, int OFF, int C>
-__device__ __forceinline__ void load_twiddles_at(cpx<T> (&w)[C], const int t, const cpx<T>* __restrict__ tw) {
-    if constexpr (NS < N) {
-        constexpr int R = pick_radix(N / NS, E);
-        constexpr int TP = N / E, Q = E / R;
-        if constexpr (NS > 1) {
-#pragma unroll
-            for (int q = 0; q < Q; ++q) {
-                const int k = (t + q * TP) % NS;
-#pragma unroll
-                for (int r = 1; r < R; ++r) w[OFF + q * (R - 1) + r - 1] = tw[k * r * (N / (NS * R))];
-            }
-            load_twiddles_at<T, N, E, NS * R, OFF + Q * (R - 1), C>(w, t, tw);
-        } else {
-            load_twiddles_at<T, N, E, NS * R, OFF, C>(w, t, tw);
-        }
-    }
-}
-
-// Fill w with thread t's twiddles (tw: the length-N table, e.g. in LDS).
-template <typename T, int N, int E, int C>
-__device__ __forceinline__ void load_twiddles(cpx<T> (&w)[C], const int t, const cpx<T>* __restrict__ tw) {
-    static_assert(C == tw_count(N, E), "twiddle register count");
-    load_twiddles_at<T, N, E, 1, 0, C>(w, t, tw);
-}
-
-// Stockham stages as in fft_stages_pp, with the twiddles taken from
-// registers (w, filled by load_twiddles) instead of a table.
-template <typename T, int N, int E, int DIR, int NS, int S, int OFF, class Lds, int C>
-__device__ __forceinline__ void fft_stages_ppr(cpx<T> (&v)[E], const int t, const Lds& l0, const Lds& l1,
-                                               const cpx<T> (&w)[C]) {
-    constexpr int R = pick_radix(N / NS, E);
-    static_assert(R > 1, "length not supported by the radix set");
-    constexpr int TP = N / E;
-    constexpr int Q = E / R;
-    constexpr bool LAST = (NS * R == N);
-    const Lds& lds = (S % 2 == 0) ? l0 : l1;
-    cpx<T> out[E];
-#pragma unroll
-    for (int q = 0; q < Q; ++q) {
-        const int b = t + q * TP;
-        cpx<T> x[R];
-#pragma unroll
-        for (int r = 0; r < R; ++r) x[r] = v[q + r * Q];
-        if constexpr (NS > 1) {
-#pragma unroll
-            for (int r = 1; r < R; ++r) x[r] = twmul<DIR>(x[r], w[OFF + q * (R - 1) + r - 1]);
-        }
-        dft<R, DIR>(x);
-        if constexpr (LAST) {
-#pragma unroll
-            for (int r = 0; r < R; ++r) out[q + r * Q] = x[r];
-        } else {
-            const int k = b % NS;
-            const int base = (b / NS) * NS * R + k;
-#pragma unroll
-            for (int r = 0; r < R; ++r) lds[base + r * NS] = x[r];
-        }
-    }
-    if constexpr (LAST) {
-#pragma unroll
-        for (int e = 0; e < E; ++e) v[e] = out[e];
-        if constexpr (S % 2 == 1) __syncthreads();  // odd number of exchanges
-    } else {
-        __syncthreads();
-#pragma unroll
-        for (int e = 0; e < E; ++e) v[e] = lds[t + e * TP];
-        constexpr int NOFF = (NS > 1) ? OFF + Q * (R - 1) : OFF;
-        fft_stages_ppr<T, N, E, DIR, NS * R, S + 1, NOFF, Lds, C>(v, t, l0, l1, w);
-    }
-}
-
-// Two-buffer transform with register twiddles (see fft_stages_pp for the
-// synchronisation contract).
-template <typename T, int N, int E, int DIR, class Lds, int C>
-__device__ __forceinline__ void fft_pencil_ppr(cpx<T> (&v)[E], const int t, const Lds& l0, const Lds& l1,
-                                               const cpx<T> (&w)[C]) {
-    static_assert(N % E == 0, "E must divide N");
-    static_assert(num_stages(N, E) > 0, "length not supported");
-    fft_stages_ppr<T, N, E, DIR, 1, 0, 0, Lds, C>(v, t, l0, l1, w);
-}
-
-// Length-N transform with two LDS buffers (see fft_stages_pp); every thread
-// of the workgroup must call it, and between two calls the buffers may be
-// used for nothing else.
+// Two-buffer transform (SYNC_PP): every thread of the workgroup calls it,
+// and between two calls the buffers are used for nothing else.
 template <typename T, int N, int E, int DIR, class Lds>
 __device__ __forceinline__ void fft_pencil_pp(cpx<T> (&v)[E], const int t, const Lds& l0, const Lds& l1,
                                               const cpx<T>* __restrict__ tw) {
-    static_assert(N % E == 0, "E must divide N");
-    static_assert(num_stages(N, E) > 0, "length not supported");
-    fft_stages_pp<T, N, E, DIR, 1, 0, Lds>(v, t, l0, l1, tw);
+    static_assert(N % E == 0 && num_stages(N, E) > 0, "length not supported");
+    fft_stages<T, N, E, DIR, 1, 0, SYNC_PP, false>(v, t, l0, l1, TwTable<T>{tw});
+}
+template <typename T, int N, int E, int DIR, class Lds, int C>
+__device__ __forceinline__ void fft_pencil_ppr(cpx<T> (&v)[E], const int t, const Lds& l0, const Lds& l1,
+                                               const cpx<T> (&w)[C]) {
+    static_assert(N % E == 0 && num_stages(N, E) > 0, "length not supported");
+    fft_stages<T, N, E, DIR, 1, 0, SYNC_PP, false>(v, t, l0, l1, TwRegs<T, C>{w});
 }
 
-// Single transform per workgroup with one exchange: one LDS buffer and one
-// barrier (nothing reuses the buffer afterwards).
+// Single transform per workgroup with one exchange (SYNC_ONCE).
 template <typename T, int N, int E, int DIR, class Lds>
 __device__ __forceinline__ void fft_pencil_once(cpx<T> (&v)[E], const int t, const Lds& l0,
                                                 const cpx<T>* __restrict__ tw) {
     static_assert(num_stages(N, E) == 2, "one exchange only");
-    fft_stages_pp<T, N, E, DIR, 1, 0, Lds, false>(v, t, l0, l0, tw);
+    fft_stages<T, N, E, DIR, 1, 0, SYNC_ONCE, false>(v, t, l0, l0, TwTable<T>{tw});
 }
 
 }  // namespace vofl

@@ -173,6 +173,16 @@ __global__ __launch_bounds__(P*(N / E)) void k_contig(ContigArgs<T, TI> a) {
     // a pencil's TP threads are consecutive and TP divides 64: every
     // transform stays inside one wavefront
     constexpr bool WV = (TP <= 64) && (64 % TP == 0);
+    // the inverse transforms of the terms use this thread's twiddles from
+    // registers (one table read per kernel instead of one per transform)
+    constexpr bool TWREG = E <= 8 && tw_count(N, E) > 0 && tw_count(N, E) <= 16;
+    constexpr int TWC = TWREG ? tw_count(N, E) : 1;
+    cpx<T> twr[TWC];
+    if constexpr (TWREG) load_twiddles<T, N, E, TWC>(twr, t, tw_s);
+    auto inv_fft = [&](cpx<T> (&x)[E]) __attribute__((always_inline)) {
+        if constexpr (TWREG) fft_pencil_r<T, N, E, +1, LdsPencil<T>, WV, TWC>(x, t, lds, twr);
+        else fft_pencil<T, N, E, +1, LdsPencil<T>, WV>(x, t, lds, tw_s);
+    };
 
     cpx<double> uh[E], vh[E];
     if (a.in_kind == IN_KICK) {
@@ -256,7 +266,7 @@ __global__ __launch_bounds__(P*(N / E)) void k_contig(ContigArgs<T, TI> a) {
             cpx<T> x[E];
 #pragma unroll
             for (int e = 0; e < E; ++e) x[e] = from_d<T>(vh[e]);
-            fft_pencil<T, N, E, +1, LdsPencil<T>, WV>(x, t, lds, tw_s);
+            inv_fft(x);
             if (active) {
                 cpx<T>* d = dst0 + (long long)(a.M + 1) * a.H;
 #pragma unroll
@@ -270,7 +280,7 @@ __global__ __launch_bounds__(P*(N / E)) void k_contig(ContigArgs<T, TI> a) {
             cpx<T> x[E];
 #pragma unroll
             for (int e = 0; e < E; ++e) x[e] = from_d<T>(uh[e]);
-            fft_pencil<T, N, E, +1, LdsPencil<T>, WV>(x, t, lds, tw_s);
+            inv_fft(x);
             if (active) {
                 cpx<T>* d = dst0 + (long long)m * a.H;
 #pragma unroll
@@ -288,7 +298,7 @@ __global__ __launch_bounds__(P*(N / E)) void k_contig(ContigArgs<T, TI> a) {
             cpx<T> x[E];
 #pragma unroll
             for (int e = 0; e < E; ++e) x[e] = from_d<T>(uh[e]);
-            fft_pencil<T, N, E, +1, LdsPencil<T>, WV>(x, t, lds, tw_s);
+            inv_fft(x);
             if (active) {
                 cpx<T>* d = dst0 + (long long)(2 * m) * a.H;
 #pragma unroll
@@ -296,7 +306,7 @@ __global__ __launch_bounds__(P*(N / E)) void k_contig(ContigArgs<T, TI> a) {
             }
 #pragma unroll
             for (int e = 0; e < E; ++e) x[e] = from_d<T>(vh[e]);
-            fft_pencil<T, N, E, +1, LdsPencil<T>, WV>(x, t, lds, tw_s);
+            inv_fft(x);
             if (active) {
                 cpx<T>* d = dst0 + (long long)(2 * m + 1) * a.H;
 #pragma unroll
@@ -315,7 +325,7 @@ __global__ __launch_bounds__(P*(N / E)) void k_contig(ContigArgs<T, TI> a) {
             cpx<T> x[E];
 #pragma unroll
             for (int e = 0; e < E; ++e) x[e] = from_d<T>(f == 0 ? uh[e] : vh[e]);
-            fft_pencil<T, N, E, +1, LdsPencil<T>, WV>(x, t, lds, tw_s);
+            inv_fft(x);
             if (active) {
                 cpx<T>* d = dst0 + (long long)f * a.H;
 #pragma unroll
@@ -638,7 +648,7 @@ void k_c2r0(C2RArgs<T> a) {
     // and S2 = sum delta^m t2_m (delta^m rounded once) and multiplied by -A,
     // -B at the end; these sums are small corrections to the m = 0 term, and
     // the split saves three instructions per point and transform.
-    constexpr bool SPLIT = MODE == C2R_KICK && sizeof(T) == 4;
+    constexpr bool SPLIT = MODE == C2R_KICK && sizeof(T) == 4 && E <= 8;
     T acc[E], cA[E], cB[E];
     T S1[SPLIT ? E : 1], S2[SPLIT ? E : 1];
     double dm[E];
