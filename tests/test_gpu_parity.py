@@ -143,8 +143,10 @@ def test_step_1d_c1(precision):
     assert p.sync_status() == 0
     ru, rv = O.tsfp2_seismic(as_seen(c["u0"], precision), c["v0"], c["gamma"], c["c0"], c["omega0"],
                              c["lo"], c["hi"], c["M"], c["dt"], c["steps"])
-    assert rel_l2(host(u), ru) <= tol(precision)
-    assert rel_l2(host(v), rv) <= (tol(precision) * 10 if precision == "fp32" else 1e-11)
+    eu, ev = rel_l2(host(u), ru), rel_l2(host(v), rv)
+    say(f"  rel L2 u {eu:.2e} v {ev:.2e}")
+    assert eu <= tol(precision), eu
+    assert ev <= tol(precision), ev
 
 
 STEP_CASES = [
@@ -175,7 +177,7 @@ def test_step_nd_vs_oracle(case, precision):
     eu, ev = rel_l2(host(u), ru), rel_l2(host(v), rv)
     say(f"  rel L2 u {eu:.2e} v {ev:.2e}")
     assert eu <= tol(precision), eu
-    assert ev <= tol(precision) * 10, ev
+    assert ev <= tol(precision), ev
 
 
 def test_step_zero_steps_is_identity():
@@ -306,4 +308,4 @@ def test_axis0_variants_apply_and_step(case, precision, variant):
     eu, ev = rel_l2(host(u), ru), rel_l2(host(v), rv)
     say(f"  rel L2 u {eu:.2e} v {ev:.2e}")
     assert eu <= tol(precision), eu
-    assert ev <= tol(precision) * 10, ev
+    assert ev <= tol(precision), ev
