@@ -87,9 +87,14 @@ hipError_t Launch<T>::mid(int N, int dir, const MidArgs<T>& a, int planes, int i
     case n: {                                                                           \
         constexpr int E = e_mid(n), W = tile_width<T, n>();                             \
         constexpr int W2 = (2 * W * n * int(sizeof(cpx<T>)) <= 67584) ? 2 * W : W;      \
-        const int w = (variant == 1) ? W2 : W;                                          \
+        constexpr int W4 = (4 * W * n * int(sizeof(cpx<T>)) <= 135168 &&               \
+                            4 * W * (n / E) <= 1024) ? 4 * W : W2;                      \
+        const int w = (variant == 2) ? W4 : (variant == 1) ? W2 : W;                   \
         dim3 grid(planes * ((a.n2 + w - 1) / w), items * a.nf);                         \
-        if (variant == 1 && W2 != W) {                                                  \
+        if (variant == 2 && W4 != W2) {                                                 \
+            if (dir < 0) k_mid<T, n, E, W4, -1><<<grid, dim3(W4 * (n / E)), 0, s>>>(a); \
+            else k_mid<T, n, E, W4, +1><<<grid, dim3(W4 * (n / E)), 0, s>>>(a);        \
+        } else if (variant >= 1 && W2 != W) {                                           \
             if (dir < 0) k_mid<T, n, E, W2, -1><<<grid, dim3(W2 * (n / E)), 0, s>>>(a); \
             else k_mid<T, n, E, W2, +1><<<grid, dim3(W2 * (n / E)), 0, s>>>(a);        \
         } else {                                                                        \
@@ -109,9 +114,11 @@ int Launch<T>::mid_tile(int N, int variant) {
     switch (N) {
 #define C_(n)                                                                           \
     case n: {                                                                           \
-        constexpr int W = tile_width<T, n>();                                           \
+        constexpr int W = tile_width<T, n>(), E = e_mid(n);                             \
         constexpr int W2 = (2 * W * n * int(sizeof(cpx<T>)) <= 67584) ? 2 * W : W;      \
-        return variant == 1 ? W2 : W;                                                   \
+        constexpr int W4 = (4 * W * n * int(sizeof(cpx<T>)) <= 135168 &&               \
+                            4 * W * (n / E) <= 1024) ? 4 * W : W2;                      \
+        return variant == 2 ? W4 : variant == 1 ? W2 : W;                               \
     }
         VOFL_MULTI_SIZES(C_)
 #undef C_

@@ -671,7 +671,9 @@ int autotune(vofl_plan_s* p, int steps) {
     for (int c : {0, 2, 5, 6, 11, 12})
         if (Launch<T>::c2r_variant_exists(g.n[0], c)) c2r.push_back(c);
     mid.push_back(0);
-    if (g.ndim == 3 && Launch<T>::mid_tile(g.n[1], 1) != Launch<T>::mid_tile(g.n[1], 0)) mid.push_back(1);
+    if (g.ndim == 3)
+        for (int m = 1; m <= 2; ++m)
+            if (Launch<T>::mid_tile(g.n[1], m) != Launch<T>::mid_tile(g.n[1], m - 1)) mid.push_back(m);
     const bool timing = p->timing;
     p->timing = false;
     double best = 1e300;

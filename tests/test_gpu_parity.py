@@ -309,3 +309,33 @@ def test_axis0_variants_apply_and_step(case, precision, variant):
     say(f"  rel L2 u {eu:.2e} v {ev:.2e}")
     assert eu <= tol(precision), eu
     assert ev <= tol(precision), ev
+
+
+@pytest.mark.parametrize("mid_variant", [0, 1, 2])
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_mid_variants_apply_and_step(precision, mid_variant):
+    """Every middle-axis tile width (the 256-point axis 1 with a ragged last
+    axis of 96 columns) against the oracle."""
+    import os
+    shape, lo, hi = (16, 256, 96), (-2.0, -16.0, -6.0), (2.0, 16.0, 6.0)
+    Q, gamma = _grf_gamma(shape, lo, hi, 77)
+    u0 = gaussian_pulse(shape, lo, hi, [0.2, -1.0, 0.5])
+    say(f"mid variant {mid_variant} {shape} {precision}")
+    os.environ["VOFL_MID_VARIANT"] = str(mid_variant)
+    try:
+        p = _plan(shape, lo, hi, precision, Q=Q, M=4, dt=2e-3, max_batch=2)
+    finally:
+        del os.environ["VOFL_MID_VARIANT"]
+    assert p.info()["mid_variant"] == mid_variant
+    u_in = as_seen(u0, precision)
+    out = host(p.apply(2, dev(u0, precision))).reshape(shape)
+    ref = O.mterm_apply(u_in, 0.5 + gamma, lo, hi, 4)
+    assert rel_l2(out, ref) <= tol(precision), rel_l2(out, ref)
+    u, v = dev(u0, precision), dev(np.zeros(shape), precision)
+    p.step(u, v, 3)
+    assert p.sync_status() == 0
+    ru, rv = O.tsfp2_seismic(u_in, np.zeros(shape), gamma, 1.0, 1.0, lo, hi, 4, 2e-3, 3)
+    eu, ev = rel_l2(host(u), ru), rel_l2(host(v), rv)
+    say(f"  rel L2 u {eu:.2e} v {ev:.2e}")
+    assert eu <= tol(precision), eu
+    assert ev <= tol(precision), ev
