@@ -68,7 +68,7 @@ import numpy as np
 __all__ = [
     "fft_bins", "wavenumbers", "mu_squared", "gamma_from_Q",
     "seismic_coefficients", "dense_dft", "dense_apply", "dense_matrix_1d",
-    "mterm_apply", "seismic_op_order", "tsfp2_generic", "damped_propagator",
+    "mterm_apply", "seismic_op_order", "tsfp2_generic", "lffp_generic", "damped_propagator",
     "tsfp2_seismic", "weighted_l2", "rel_l2", "mterm_apply_at", "set_fft_workers",
 ]
 
@@ -372,6 +372,51 @@ def tsfp2_generic(phi, psi, s, kappa: float, lo, hi, M: int, dt: float,
             v2 = v1 + dt * rhs
             uh, vh = exact_part(_to_spec(u1), _to_spec(v2), dt / 2.0)
     return _to_phys(uh), _to_phys(vh)
+
+
+def lffp_generic(phi, psi, s, kappa: float, lo, hi, M: int, dt: float,
+                 nsteps: int, f=None):
+    """Leap-frog Fourier pseudospectral scheme (3.4) for u_tt = -kappa
+    (-Lap)^{s(x)} u + f(u) on a periodic box, with (2.13) as the operator.
+
+    u^0 = phi, u^1 = phi + dt psi + dt^2/2 F(phi) (the start (3.4b, c), as
+    in (3.3)), then u^{n+1} = 2 u^n - u^{n-1} + dt^2 F(u^n), where
+    F(w) = -kappa (-Lap)^{s(x)}_{h,M} w + f(w). Returns (u^{nsteps-1},
+    u^{nsteps}) (with u^{-1} taken as phi for nsteps = 0); non-finite values
+    are propagated.
+    """
+    u = np.asarray(phi, dtype=np.float64)
+    s = np.broadcast_to(np.asarray(s, dtype=np.float64), u.shape)
+    s0 = float(np.mean(s))
+    delta = s - s0
+    mu2 = mu_squared(u.shape, lo, hi)
+    nz = mu2 > 0.0
+    lnmu2 = np.zeros_like(mu2)
+    lnmu2[nz] = np.log(mu2[nz])
+    base = np.zeros_like(mu2)
+    base[nz] = mu2[nz] ** s0
+    # loop-invariant factors of (2.13): l_m |mu|^{2 s0} and delta^m, m = 0..M
+    coefs = [lnmu2 ** m / math.factorial(m) * base for m in range(M + 1)]
+    dpow = [delta ** m for m in range(M + 1)]
+
+    def F(w):
+        wh = _to_spec(w)
+        lw = np.zeros(w.shape)
+        for m in range(M + 1):
+            lw += dpow[m] * _to_phys(coefs[m] * wh)
+        out = -kappa * lw
+        if f is not None:
+            out = out + f(w)
+        return out
+
+    if nsteps == 0:
+        return u.copy(), u.copy()
+    with np.errstate(all="ignore"):
+        prev = u
+        cur = u + dt * np.asarray(psi, dtype=np.float64) + 0.5 * dt * dt * F(u)
+        for _ in range(nsteps - 1):
+            prev, cur = cur, 2.0 * cur - prev + dt * dt * F(cur)
+    return prev, cur
 
 
 # ---------------------------------------------------------------------------
