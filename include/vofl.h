@@ -125,6 +125,25 @@ int vofl_step(vofl_plan_t plan, void* u, void* v, int nsteps, void* stream);
 int vofl_solve(vofl_plan_t plan, const void* u0, const void* v0, int nsteps,
                void* u, void* v, void* stream);
 
+/* Leap-frog Fourier pseudospectral scheme LFFP (eq. (3.4)) for the generic
+ * model (1.5): u^{n+1} = 2 u^n - u^{n-1} + dt^2 (-kappa L u^n + lambda
+ * (u^n)^3), with L the M-term operator (2.13) of the plan's s(x). Plans of
+ * the seismic model return VOFL_ERR_UNSUPPORTED (the paper defines the
+ * scheme for (1.5)).
+ *
+ * vofl_lffp_start: the start (3.4b, c): u_prev = phi and
+ * u = phi + dt psi + dt^2/2 (-kappa L phi + lambda phi^3).
+ * vofl_lffp_step: nsteps >= 0 steps on (u_prev, u) = (u^{n-1}, u^n), in
+ * place; on return they hold (u^{n+nsteps-1}, u^{n+nsteps}).
+ * All fields: device, batch * N values each, plan precision; u_prev != u
+ * (the inputs of vofl_lffp_start may alias the outputs). Within one call the
+ * state is carried in FP64 (in registers in 1D, in plan memory in 2D/3D).
+ * Asynchronous on stream; a non-finite value sets the device flag reported by
+ * vofl_sync_status. */
+int vofl_lffp_start(vofl_plan_t plan, const void* phi, const void* psi, void* u_prev, void* u,
+                    void* stream);
+int vofl_lffp_step(vofl_plan_t plan, void* u_prev, void* u, int nsteps, void* stream);
+
 /* vofl_step replayed from a HIP graph (for callers that step the same
  * buffers repeatedly). The first call with a given (u, v, nsteps) captures
  * vofl_step's launch sequence on an internal stream into a graph and

@@ -450,7 +450,26 @@ struct C2RArgs {
     T* r1;                  // export: v
     long long Nreal;
     int* flag;              // set to 1 on a non-finite kick value
+    // leap-frog (apply mode with lffp = 1): FP64 fields of item b at
+    // s_prev + b*Nreal, s_cur + b*Nreal; per point
+    //   new = lf_cb*cur + lf_ca*prev + lf_cf*(-kappa acc + lambda cur^3),
+    //   prev <- cur, cur <- new (acc = the operator (2.13) applied to cur)
+    int lffp;
+    double* s_prev;
+    double* s_cur;
+    double lf_cb, lf_ca, lf_cf;
 };
+
+// One leap-frog update (3.4a) at a point (see C2RArgs); returns false if the
+// new value is not finite.
+__device__ __forceinline__ bool lffp_point(double* prev, double* cur, double Lu, double kappa, double lambda,
+                                           double cb, double ca, double cf) {
+    const double u = *cur;
+    const double nw = cb * u + ca * (*prev) + cf * (-kappa * Lu + lambda * u * u * u);
+    *prev = u;
+    *cur = nw;
+    return isfinite(nw);
+}
 
 // Y = a + i b, with a, b the Hermitian extensions of two half columns.
 template <typename T, int N, int W>
@@ -767,9 +786,21 @@ void k_c2r0(C2RArgs<T> a) {
     }
     if constexpr (MODE == C2R_APPLY) {
         if (active) {
-            T* o = a.r0 + (long long)item * a.Nreal + colc;
+            if (a.lffp) {
+                const long long ib = (long long)item * a.Nreal + colc;
+                bool ok = true;
 #pragma unroll
-            for (int e = 0; e < E; ++e) o[(long long)(t + TP * e) * a.inner] = acc[e];
+                for (int e = 0; e < E; ++e) {
+                    const long long ix = ib + (long long)(t + TP * e) * a.inner;
+                    ok &= lffp_point(a.s_prev + ix, a.s_cur + ix, double(acc[e]), sc.kappa0, sc.lambda, a.lf_cb,
+                                     a.lf_ca, a.lf_cf);
+                }
+                if (!ok) a.flag[0] = 1;
+            } else {
+                T* o = a.r0 + (long long)item * a.Nreal + colc;
+#pragma unroll
+                for (int e = 0; e < E; ++e) o[(long long)(t + TP * e) * a.inner] = acc[e];
+            }
         }
         return;
     }
@@ -962,10 +993,21 @@ __global__ __launch_bounds__(64 * NW_) void k_c2r0w(C2RArgs<T> a) {
         for (int e = 0; e < E; ++e) ost[(t + TP * e) * W + c] = acc[e];
         __syncthreads();
         T* o = a.r0 + (long long)item * a.Nreal;
+        bool ok = true;
         for (int i = threadIdx.x; i < N * W; i += NT) {
             const int row = i / W, cg = col0 + i % W;
-            if (cg < a.inner) o[(long long)row * a.inner + cg] = ost[i];
+            if (cg < a.inner) {
+                const long long ix = (long long)row * a.inner + cg;
+                if (a.lffp) {
+                    const long long iz = (long long)item * a.Nreal + ix;
+                    ok &= lffp_point(a.s_prev + iz, a.s_cur + iz, double(ost[i]), sc.kappa0, sc.lambda, a.lf_cb,
+                                     a.lf_ca, a.lf_cf);
+                } else {
+                    o[ix] = ost[i];
+                }
+            }
         }
+        if (!ok) a.flag[0] = 1;
         return;
     }
     // kick: right-hand side, finiteness flag, forward transform, half rows out
@@ -1019,6 +1061,7 @@ struct Args1D {
     int M, op, nsteps, model;
     double dt, invN;
     int* flag;
+    double lf_cb, lf_ca, lf_cf;   // leap-frog first-step coefficients (k_1d_lffp)
 };
 
 template <typename T, int N, int E>
@@ -1272,6 +1315,128 @@ __global__ __launch_bounds__(N / E) void k_1d_step(Args1D<T> a) {
     for (int e = 0; e < E; ++e) {
         uo[t + TP * e] = y[e].x;
         vo[t + TP * e] = y[e].y;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// element-wise precision conversion (leap-frog state in and out)
+// ---------------------------------------------------------------------------
+template <typename TI, typename TO>
+__global__ __launch_bounds__(256) void k_convert(const TI* __restrict__ in, TO* __restrict__ out, long long n) {
+    for (long long i = blockIdx.x * 256LL + threadIdx.x; i < n; i += (long long)gridDim.x * 256LL)
+        out[i] = TO(in[i]);
+}
+
+// ---------------------------------------------------------------------------
+// 1D leap-frog (3.4): one workgroup per field, the state in FP64 registers
+// for all nsteps steps; (u_in, v_in) = (cur, prev) in, (u_out, v_out) =
+// (cur, prev) out (may alias the inputs: every value is read before any is
+// written, by the thread that owns it). Generic model: kappa0 = kappa.
+// ---------------------------------------------------------------------------
+template <typename T, int N, int E>
+__global__ __launch_bounds__(N / E) void k_1d_lffp(Args1D<T> a) {
+    constexpr int TP = N / E;
+    __shared__ cpx<double> lds_raw[LdsPencil<double>::footprint(N)];
+    const LdsPencil<double> lds64{lds_raw};
+    const LdsPencil<T> lds{reinterpret_cast<cpx<T>*>(lds_raw)};
+    constexpr int NTW = (N <= 1024) ? N : 1;
+    __shared__ cpx<double> tw64_l[NTW];
+    __shared__ cpx<T> tw_l[NTW];
+    const cpx<double>* tw64_s = a.tw64;
+    const cpx<T>* tw_s = a.tw;
+    if constexpr (N <= 1024) {
+        stage_twiddles<double, N>(tw64_l, a.tw64);
+        stage_twiddles<T, N>(tw_l, a.tw);
+        tw64_s = tw64_l;
+        tw_s = tw_l;
+    }
+    // long transforms keep ln|mu|^2 and |mu|^{2 s0} of their points in LDS
+    // (registers would spill), shorter ones in registers
+    constexpr bool LP_LDS = N > 1024;
+    __shared__ double lp_s[LP_LDS ? 2 * N : 1];
+    const int t = threadIdx.x;
+    const int item = blockIdx.x;
+    const SolveScalars sc = a.sc[item * a.sc_stride];
+    double cur[E], prev[E], Lr[LP_LDS ? 1 : E], Pr[LP_LDS ? 1 : E], dl[E];
+    auto Lv = [&](int e) __attribute__((always_inline)) -> double {
+        if constexpr (LP_LDS) return lp_s[t + TP * e];
+        else return Lr[e];
+    };
+    auto Pv = [&](int e) __attribute__((always_inline)) -> double {
+        if constexpr (LP_LDS) return lp_s[N + t + TP * e];
+        else return Pr[e];
+    };
+    const double* dd = a.delta + (long long)item * a.coef_stride;
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+        const int j = t + TP * e;
+        cur[e] = double(a.u_in[(long long)item * N + j]);
+        prev[e] = double(a.v_in[(long long)item * N + j]);
+        const double m2 = a.mu2[j];
+        double Le = 0.0, Pe = 0.0;
+        if (m2 > 0.0) {
+            Le = log(m2);
+            Pe = exp(sc.sig1 * Le);
+        }
+        if constexpr (LP_LDS) {
+            lp_s[j] = Le;   // read back only by this thread
+            lp_s[N + j] = Pe;
+        } else {
+            Lr[e] = Le;
+            Pr[e] = Pe;
+        }
+        dl[e] = dd[j];
+    }
+    bool ok = true;
+    for (int step = 0; step < a.nsteps; ++step) {
+        const double cb = step == 0 ? a.lf_cb : 2.0, ca = step == 0 ? a.lf_ca : -1.0;
+        const double cf = step == 0 ? a.lf_cf : a.dt * a.dt;
+        cpx<double> x[E];
+#pragma unroll
+        for (int e = 0; e < E; ++e) x[e] = {cur[e], 0.0};
+        fft_pencil<double, N, E, -1>(x, t, lds64, tw64_s);
+        cpx<double> r[E];
+        double acc[E], dp[E];
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+            r[e] = {Pv(e) * x[e].x * a.invN, Pv(e) * x[e].y * a.invN};
+            acc[e] = 0.0;
+            dp[e] = 1.0;
+        }
+        for (int m = 0; m <= a.M; m += 2) {
+            const bool pair = (m + 1 <= a.M);
+            cpx<T> y[E];
+#pragma unroll
+            for (int e = 0; e < E; ++e) {
+                const cpx<double> x0 = r[e];
+                const double f = Lv(e) / double(m + 1);
+                const cpx<double> x1 = pair ? cpx<double>{x0.x * f, x0.y * f} : cpx<double>{0.0, 0.0};
+                y[e] = {T(x0.x - x1.y), T(x0.y + x1.x)};
+                const double g = pair ? Lv(e) / double(m + 2) : 0.0;
+                r[e] = {x1.x * g, x1.y * g};
+            }
+            fft_pencil<T, N, E, +1>(y, t, lds, tw_s);
+#pragma unroll
+            for (int e = 0; e < E; ++e) {
+                acc[e] += dp[e] * (double(y[e].x) + dl[e] * double(y[e].y));
+                dp[e] *= dl[e] * dl[e];
+            }
+        }
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+            const double u = cur[e];
+            const double nw = cb * u + ca * prev[e] + cf * (-sc.kappa0 * acc[e] + sc.lambda * u * u * u);
+            ok &= isfinite(nw);
+            prev[e] = u;
+            cur[e] = nw;
+        }
+    }
+    if (!ok) a.flag[0] = 1;
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+        const int j = t + TP * e;
+        a.u_out[(long long)item * N + j] = T(cur[e]);
+        a.v_out[(long long)item * N + j] = T(prev[e]);
     }
 }
 

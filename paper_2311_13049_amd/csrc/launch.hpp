@@ -43,6 +43,10 @@ struct Launch {
     static hipError_t c2r0(int N, const C2RArgs<T>& a, int items, hipStream_t s, int variant = 0);
     static hipError_t d1_apply(int N, const Args1D<T>& a, int items, hipStream_t s);
     static hipError_t d1_step(int N, const Args1D<T>& a, int items, hipStream_t s);
+    static hipError_t d1_lffp(int N, const Args1D<T>& a, int items, hipStream_t s);
+    // element-wise T <-> FP64 copies of n values
+    static hipError_t to_f64(const T* in, double* out, long long n, hipStream_t s);
+    static hipError_t from_f64(const double* in, T* out, long long n, hipStream_t s);
 };
 
 extern template struct Launch<float>;

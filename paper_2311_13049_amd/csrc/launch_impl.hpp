@@ -271,4 +271,36 @@ hipError_t Launch<T>::d1_step(int N, const Args1D<T>& a, int items, hipStream_t 
     }
 }
 
+template <typename T>
+hipError_t Launch<T>::d1_lffp(int N, const Args1D<T>& a, int items, hipStream_t s) {
+    switch (N) {
+#define C_(n)                                                                           \
+    case n: {                                                                           \
+        constexpr int E = e_1d(n);                                                      \
+        k_1d_lffp<T, n, E><<<dim3(items), dim3(n / E), 0, s>>>(a);                      \
+        return hipGetLastError();                                                       \
+    }
+        VOFL_1D_SIZES(C_)
+#undef C_
+        default: return hipErrorInvalidValue;
+    }
+}
+
+inline unsigned convert_blocks(long long n) {
+    const long long b = (n + 255) / 256;
+    return unsigned(b < 8192 ? (b > 0 ? b : 1) : 8192);
+}
+
+template <typename T>
+hipError_t Launch<T>::to_f64(const T* in, double* out, long long n, hipStream_t s) {
+    k_convert<T, double><<<dim3(convert_blocks(n)), dim3(256), 0, s>>>(in, out, n);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t Launch<T>::from_f64(const double* in, T* out, long long n, hipStream_t s) {
+    k_convert<double, T><<<dim3(convert_blocks(n)), dim3(256), 0, s>>>(in, out, n);
+    return hipGetLastError();
+}
+
 }  // namespace vofl

@@ -156,6 +156,8 @@ int derive(const vofl_desc* d, Geometry& g) {
         bytes += (size_t)slots * g.H * celt;                  // work slots
         g.stage_fields = std::max(2 * g.batch, g.max_batch);
         bytes += (size_t)g.stage_fields * g.H * 16;           // FP64 state / forward staging
+        if (d->model == VOFL_MODEL_GENERIC)
+            bytes += (size_t)2 * g.batch * g.Nreal * 8;        // FP64 leap-frog state (u^{n-1}, u^n)
     }
     g.bytes = bytes;
     if (d->hbm_budget && bytes > d->hbm_budget)
@@ -191,6 +193,7 @@ struct vofl_plan_s {
     void* tw[3] = {nullptr, nullptr, nullptr};      // working precision
     cpx<double>* tw64[3] = {nullptr, nullptr, nullptr};
     double* delta = nullptr;
+    double* LS = nullptr;              // leap-frog FP64 state: u^{n-1} of every solve, then u^n
     void* A = nullptr;
     void* B = nullptr;
     SolveScalars* sc = nullptr;
@@ -365,6 +368,9 @@ int upload_tables(vofl_plan_s* p, const std::vector<double>& delta, const std::v
         // FP64 staging of forward transforms (apply fields use it from the start)
         if ((rc = dalloc(p, (cpx<double>**)&p->U, (size_t)g.stage_fields * g.H * sizeof(cpx<double>)))) return rc;
         p->V = (cpx<double>*)p->U + (size_t)g.batch * g.H;
+        if (p->model == VOFL_MODEL_GENERIC &&
+            (rc = dalloc(p, &p->LS, (size_t)2 * g.batch * g.Nreal * sizeof(double))))
+            return rc;
     }
     return VOFL_OK;
 }
@@ -448,13 +454,21 @@ C2RArgs<T> c2r_base(vofl_plan_s* p) {
     return c;
 }
 
-template <typename T>
-int apply_multi(vofl_plan_s* p, int op, const T* u, T* out, int nf, hipStream_t s) {
+// leap-frog update fused into the apply's last pass (see C2RArgs)
+struct LffpPass {
+    double cb, ca, cf;
+    double* prev;
+    double* cur;
+};
+
+template <typename T, typename TIN = T>
+int apply_multi(vofl_plan_s* p, int op, const TIN* u, T* out, int nf, hipStream_t s,
+                const LffpPass* lf = nullptr) {
     const Geometry& g = p->g;
     const long long AS = (long long)g.apply_slots * g.H;  // item stride of the term slots
     cpx<T>* W = (cpx<T>*)p->work;
     cpx<double>* stage = (cpx<double>*)p->U;
-    hipError_t e = forward_to_stage<T>(p, u, stage, nf, s);
+    hipError_t e = forward_to_stage<TIN>(p, u, stage, nf, s);
     if (e != hipSuccess) return hip_fail(e, "r2c0 launch");
     if ((e = mid<double>(p, "mid_apply_fwd", -1, stage, g.H, 1, nf, p->tw64[1 % g.ndim], s)) != hipSuccess)
         return hip_fail(e, "mid launch");
@@ -478,10 +492,36 @@ int apply_multi(vofl_plan_s* p, int op, const T* u, T* out, int nf, hipStream_t 
     c.istride = AS;
     c.mode = C2R_APPLY;
     c.r0 = out;
-    e = p->timed("c2r0_apply", s, [&] { return Launch<T>::c2r0(g.n[0], c, nf, s, p->c2r_variant); });
+    if (lf) {
+        c.lffp = 1;
+        c.s_prev = lf->prev;
+        c.s_cur = lf->cur;
+        c.lf_cb = lf->cb;
+        c.lf_ca = lf->ca;
+        c.lf_cf = lf->cf;
+    }
+    e = p->timed(lf ? "c2r0_lffp" : "c2r0_apply", s, [&] { return Launch<T>::c2r0(g.n[0], c, nf, s, p->c2r_variant); });
     if (e != hipSuccess) return hip_fail(e, "c2r0 launch");
     return VOFL_OK;
 }
+
+// nsteps leap-frog steps (3.4a) on the plan's FP64 state; the first uses
+// (cb0, ca0, cf0) in place of (2, -1, dt^2) (the start (3.4c) is such a step
+// with (1, dt, dt^2/2) on (prev, cur) = (psi, phi))
+template <typename T>
+int lffp_multi(vofl_plan_s* p, double cb0, double ca0, double cf0, int nsteps, hipStream_t s) {
+    const Geometry& g = p->g;
+    double* prev = p->LS;
+    double* cur = p->LS + (size_t)g.batch * g.Nreal;
+    for (int k = 0; k < nsteps; ++k) {
+        const LffpPass lf{k == 0 ? cb0 : 2.0, k == 0 ? ca0 : -1.0, k == 0 ? cf0 : p->dt * p->dt, prev, cur};
+        const int rc = apply_multi<T, double>(p, VOFL_OP_S1, cur, (T*)nullptr, g.batch, s, &lf);
+        if (rc) return rc;
+    }
+    return VOFL_OK;
+}
+
+
 
 template <typename T>
 int step_multi(vofl_plan_s* p, T* u, T* v, int nsteps, hipStream_t s) {
@@ -583,6 +623,37 @@ Args1D<T> args_1d(vofl_plan_s* p) {
     a.invN = 1.0 / (double)g.Nreal;
     a.flag = p->flag;
     return a;
+}
+
+// leap-frog on caller fields: (cur, prev) in, nsteps steps, (cur, prev) out
+template <typename T>
+int lffp_any(vofl_plan_s* p, const void* cur_in, const void* prev_in, void* cur_out, void* prev_out,
+             double cb0, double ca0, double cf0, int nsteps, hipStream_t s) {
+    const Geometry& g = p->g;
+    if (g.ndim == 1) {
+        Args1D<T> a = args_1d<T>(p);
+        a.u_in = (const T*)cur_in;
+        a.v_in = (const T*)prev_in;
+        a.u_out = (T*)cur_out;
+        a.v_out = (T*)prev_out;
+        a.nsteps = nsteps;
+        a.lf_cb = cb0;
+        a.lf_ca = ca0;
+        a.lf_cf = cf0;
+        hipError_t e = p->timed("1d_lffp", s, [&] { return Launch<T>::d1_lffp(a.N, a, g.batch, s); });
+        return e == hipSuccess ? VOFL_OK : hip_fail(e, "1d leap-frog launch");
+    }
+    const long long n = (long long)g.batch * g.Nreal;
+    double* prev = p->LS;
+    double* cur = p->LS + n;
+    hipError_t e = Launch<T>::to_f64((const T*)cur_in, cur, n, s);
+    if (e == hipSuccess) e = Launch<T>::to_f64((const T*)prev_in, prev, n, s);
+    if (e != hipSuccess) return hip_fail(e, "state load");
+    int rc = lffp_multi<T>(p, cb0, ca0, cf0, nsteps, s);
+    if (rc) return rc;
+    e = Launch<T>::from_f64(cur, (T*)cur_out, n, s);
+    if (e == hipSuccess) e = Launch<T>::from_f64(prev, (T*)prev_out, n, s);
+    return e == hipSuccess ? VOFL_OK : hip_fail(e, "state store");
 }
 
 template <typename T>
@@ -920,6 +991,32 @@ int vofl_solve(vofl_plan_t p, const void* u0, const void* v0, int nsteps, void* 
     if (e == hipSuccess && v0 != v) e = hipMemcpyAsync(v, v0, bytes, hipMemcpyDeviceToDevice, s);
     if (e != hipSuccess) return hip_fail(e, "initial copy");
     return vofl_step(p, u, v, nsteps, stream);
+}
+
+int vofl_lffp_start(vofl_plan_t p, const void* phi, const void* psi, void* u_prev, void* u, void* stream) {
+    if (!p) return fail(VOFL_ERR_INVALID, "plan is NULL");
+    if (!phi || !psi || !u_prev || !u) return fail(VOFL_ERR_INVALID, "phi, psi, u_prev and u must be device pointers");
+    if (u_prev == u) return fail(VOFL_ERR_INVALID, "u_prev and u must be distinct");
+    if (p->model != VOFL_MODEL_GENERIC)
+        return fail(VOFL_ERR_UNSUPPORTED, "the leap-frog scheme is provided for the generic model (1.5)");
+    hipStream_t s = (hipStream_t)stream;
+    const double dt = p->dt;
+    return p->precision == VOFL_FP32 ? lffp_any<float>(p, phi, psi, u, u_prev, 1.0, dt, 0.5 * dt * dt, 1, s)
+                                     : lffp_any<double>(p, phi, psi, u, u_prev, 1.0, dt, 0.5 * dt * dt, 1, s);
+}
+
+int vofl_lffp_step(vofl_plan_t p, void* u_prev, void* u, int nsteps, void* stream) {
+    if (!p) return fail(VOFL_ERR_INVALID, "plan is NULL");
+    if (!u_prev || !u) return fail(VOFL_ERR_INVALID, "u_prev and u must be device pointers");
+    if (u_prev == u) return fail(VOFL_ERR_INVALID, "u_prev and u must be distinct");
+    if (nsteps < 0) return fail(VOFL_ERR_INVALID, "nsteps must be >= 0");
+    if (p->model != VOFL_MODEL_GENERIC)
+        return fail(VOFL_ERR_UNSUPPORTED, "the leap-frog scheme is provided for the generic model (1.5)");
+    if (nsteps == 0) return VOFL_OK;
+    hipStream_t s = (hipStream_t)stream;
+    const double dt2 = p->dt * p->dt;
+    return p->precision == VOFL_FP32 ? lffp_any<float>(p, u, u_prev, u, u_prev, 2.0, -1.0, dt2, nsteps, s)
+                                     : lffp_any<double>(p, u, u_prev, u, u_prev, 2.0, -1.0, dt2, nsteps, s);
 }
 
 int vofl_step_batch(vofl_plan_t* plans, void** u, void** v, const int* nsteps, int count, void* stream) {

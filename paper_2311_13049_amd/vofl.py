@@ -32,7 +32,7 @@ VOFL_OP_S2 = 2
 # every function declared in include/vofl.h
 ABI_FUNCTIONS = (
     "vofl_plan", "vofl_plan_footprint", "vofl_apply", "vofl_step", "vofl_step_graph", "vofl_solve",
-    "vofl_step_batch", "vofl_sync_status", "vofl_set_timing", "vofl_kernel_times",
+    "vofl_lffp_start", "vofl_lffp_step", "vofl_step_batch", "vofl_sync_status", "vofl_set_timing", "vofl_kernel_times",
     "vofl_plan_info", "vofl_destroy", "vofl_last_error", "vofl_version",
 )
 
@@ -88,6 +88,8 @@ def load_library():
     lib.vofl_apply.argtypes = [vp, ctypes.c_int, vp, vp, ctypes.c_int, vp]
     lib.vofl_step.argtypes = [vp, vp, vp, ctypes.c_int, vp]
     lib.vofl_step_graph.argtypes = [vp, vp, vp, ctypes.c_int, vp]
+    lib.vofl_lffp_start.argtypes = [vp, vp, vp, vp, vp, vp]
+    lib.vofl_lffp_step.argtypes = [vp, vp, vp, ctypes.c_int, vp]
     lib.vofl_solve.argtypes = [vp, vp, vp, ctypes.c_int, vp, vp, vp]
     lib.vofl_step_batch.argtypes = [ctypes.POINTER(vp), ctypes.POINTER(vp), ctypes.POINTER(vp),
                                     ctypes.POINTER(ctypes.c_int), ctypes.c_int, vp]
@@ -100,6 +102,7 @@ def load_library():
     lib.vofl_last_error.restype = ctypes.c_char_p
     lib.vofl_version.restype = ctypes.c_char_p
     for name in ("vofl_plan", "vofl_plan_footprint", "vofl_apply", "vofl_step", "vofl_step_graph", "vofl_solve",
+                 "vofl_lffp_start", "vofl_lffp_step",
                  "vofl_step_batch", "vofl_sync_status", "vofl_set_timing", "vofl_kernel_times",
                  "vofl_plan_info", "vofl_destroy"):
         getattr(lib, name).restype = ctypes.c_int
@@ -178,6 +181,17 @@ def vofl_step(plan: int, u_ptr: int, v_ptr: int, nsteps: int, stream=0) -> None:
 def vofl_step_graph(plan: int, u_ptr: int, v_ptr: int, nsteps: int, stream=0) -> None:
     _check(load_library().vofl_step_graph(ctypes.c_void_p(plan), ctypes.c_void_p(u_ptr),
                                           ctypes.c_void_p(v_ptr), nsteps, ctypes.c_void_p(stream)))
+
+
+def vofl_lffp_start(plan: int, phi_ptr: int, psi_ptr: int, u_prev_ptr: int, u_ptr: int, stream=0) -> None:
+    _check(load_library().vofl_lffp_start(ctypes.c_void_p(plan), ctypes.c_void_p(phi_ptr),
+                                          ctypes.c_void_p(psi_ptr), ctypes.c_void_p(u_prev_ptr),
+                                          ctypes.c_void_p(u_ptr), ctypes.c_void_p(stream)))
+
+
+def vofl_lffp_step(plan: int, u_prev_ptr: int, u_ptr: int, nsteps: int, stream=0) -> None:
+    _check(load_library().vofl_lffp_step(ctypes.c_void_p(plan), ctypes.c_void_p(u_prev_ptr),
+                                         ctypes.c_void_p(u_ptr), nsteps, ctypes.c_void_p(stream)))
 
 
 def vofl_solve(plan: int, u0_ptr: int, v0_ptr: int, nsteps: int, u_ptr: int, v_ptr: int,
@@ -286,6 +300,22 @@ class Plan:
         self._check_tensor(v, self.batch, "v")
         vofl_step_graph(self.handle, u.data_ptr(), v.data_ptr(), int(nsteps), self._stream())
         return u, v
+
+    def lffp_start(self, phi, psi):
+        """Leap-frog start (3.4b, c): returns new tensors (u^0, u^1)."""
+        self._check_tensor(phi, self.batch, "phi")
+        self._check_tensor(psi, self.batch, "psi")
+        u_prev = self.torch.empty_like(phi)
+        u = self.torch.empty_like(phi)
+        vofl_lffp_start(self.handle, phi.data_ptr(), psi.data_ptr(), u_prev.data_ptr(), u.data_ptr(),
+                        self._stream())
+        return u_prev, u
+
+    def lffp_step(self, u_prev, u, nsteps: int):
+        self._check_tensor(u_prev, self.batch, "u_prev")
+        self._check_tensor(u, self.batch, "u")
+        vofl_lffp_step(self.handle, u_prev.data_ptr(), u.data_ptr(), int(nsteps), self._stream())
+        return u_prev, u
 
     def solve(self, u0, v0, nsteps: int):
         u = u0.clone()

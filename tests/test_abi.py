@@ -86,12 +86,20 @@ def test_valid_descriptors_and_footprint_formula():
     slots = max(2 * (M + 1) + 3, 3 * (M + 1))
     expect = (n0 + n1) * (8 + 16 + 8) + 512 * (8 + 8) + 64 + 256 + slots * H * 8 + max(2, 3) * H * 16
     assert b == expect
+    # generic model: M + 2 step slots plus the FP64 leap-frog state (2 fields)
+    d, keep = _desc(precision="fp32", max_batch=3, model="generic", gamma=None, s=np.full(512, 1.2), kappa=1.0)
+    b = V.vofl_plan_footprint(d)
+    slots = max((M + 2) + 3, 3 * (M + 1))
+    expect = (n0 + n1) * (8 + 16 + 8) + 512 * (8 + 8) + 64 + 256 + slots * H * 8 + max(2, 3) * H * 16 + 2 * 512 * 8
+    assert b == expect
 
 
 def test_null_plan_arguments_are_rejected():
     lib = V.load_library()
     assert lib.vofl_apply(None, 1, None, None, 1, None) == V.VOFL_ERR_INVALID
     assert lib.vofl_step(None, None, None, 1, None) == V.VOFL_ERR_INVALID
+    assert lib.vofl_lffp_step(None, None, None, 1, None) == V.VOFL_ERR_INVALID
+    assert lib.vofl_lffp_start(None, None, None, None, None, None) == V.VOFL_ERR_INVALID
     assert lib.vofl_destroy(None) == V.VOFL_ERR_INVALID
     assert "NULL" in V.vofl_last_error()
 
