@@ -79,7 +79,7 @@ def main():
     ap.add_argument("--M", type=int, default=16)
     ap.add_argument("--precision", default="fp32")
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--workload", default="c3", choices=("c3", "c4", "c5"))
+    ap.add_argument("--workload", default="c3", choices=("c3", "c4", "c5", "lffp"))
     ap.add_argument("--requests", type=int, default=40, help="c5: requests in the trace")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain device copy of 1 GiB five times (HBM counter calibration)")
@@ -111,6 +111,8 @@ def main():
         return bench_c4(args, torch, V, dev)
     if args.workload == "c5":
         return bench_c5(args, torch, V, dev)
+    if args.workload == "lffp":
+        return bench_lffp(args, torch, V, dev)
     n, M = args.n, args.M
     c = c3_inputs(n=n)
     prec = args.precision
@@ -308,6 +310,53 @@ def bench_c4(args, torch, V, dev):
         "plan_build_s": [g["plan_s"] for g in groups],
         "tuned_variants": [{"c2r": g["info"]["c2r_variant"], "mid": g["info"]["mid_variant"]} for g in groups],
         "status": status,
+    }
+    print(json.dumps(out), flush=True)
+
+
+def bench_lffp(args, torch, V, dev):
+    """Leap-frog scheme (3.4) for the generic model (1.5) on 256^3, M = 16, FP32:
+    one operator apply and the update per step."""
+    from workloads import gaussian_pulse, mesh
+    n, M = args.n, args.M
+    shape, lo, hi = (n, n, n), (-16.0,) * 3, (16.0,) * 3
+    X = mesh(shape, lo, hi)
+    s_field = 1.0 + 0.3 * np.sin(np.pi * X[0] / 8.0) * np.cos(np.pi * X[1] / 8.0)
+    phi = gaussian_pulse(shape, lo, hi, (0.0, 0.0, 0.0))
+    del X
+    tdt = torch.float32 if args.precision == "fp32" else torch.float64
+    plan = V.Plan(shape, lo, hi, model="generic", s=s_field, kappa=1.0, lam=1.0, M=M, dt=1e-3,
+                  precision=args.precision)
+    up, u = plan.lffp_start(torch.from_numpy(phi).to(dev, tdt), torch.zeros(shape, device=dev, dtype=tdt))
+    plan.lffp_step(up, u, args.warmup)
+    torch.cuda.synchronize()
+    plan.set_timing(True)
+    t0 = time.perf_counter()
+    plan.lffp_step(up, u, args.steps)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    kt = plan.kernel_times()
+    plan.set_timing(False)
+    step_s = (t1 - t0) / args.steps
+    elt = 4 if args.precision == "fp32" else 8
+    H = (n // 2 + 1) * n * n
+    # algorithmic bytes of the axis-0 pass with the update: M+1 term slots,
+    # delta, and the FP64 state read and written
+    alg_c2r = (M + 1) * H * 2 * elt + n ** 3 * 8 + 4 * n ** 3 * 8
+    c2r_ms, c2r_n = kt.get("c2r0_lffp", (0.0, 1))
+    out = {
+        "metric": "leap-frog (3.4) steps/s, generic model (1.5), 256^3, M=16",
+        "value": 1.0 / step_s, "unit": "steps/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": step_s * 1e3, "higher_is_better": True, "data": "synthetic",
+        "dtype": "f32" if args.precision == "fp32" else "f64",
+        "config": {"workload": f"LFFP on {n}^3 [-16,16)^3, s = 1 + 0.3 sin(pi x/8) cos(pi y/8), kappa = 1, "
+                               f"f = u^3, M = {M}, dt = 1e-3"},
+        "applies_per_s": 1.0 / step_s,
+        "gpts_M_per_s": n ** 3 * M / step_s / 1e9,
+        "kernel_ms_per_step": {k: ms / args.steps for k, (ms, _) in kt.items()},
+        "roofline_c2r0_lffp": {"bound": "hbm", "achieved": alg_c2r / (c2r_ms / c2r_n / 1e3) / 1e9 if c2r_ms else None,
+                               "peak": HBM_PEAK_GBS, "unit": "GB/s", "alg_bytes_per_launch": alg_c2r},
+        "status": plan.sync_status(),
     }
     print(json.dumps(out), flush=True)
 
