@@ -45,7 +45,8 @@ extern "C" {
 #define VOFL_ERR_DEVICE     -3  /* HIP runtime error (no device, launch failure)     */
 #define VOFL_ERR_UNSTABLE   -4  /* a non-finite value appeared (time step too large,
                                    see the stability condition (3.5))               */
-#define VOFL_ERR_UNSUPPORTED -5 /* grid size without a compiled FFT length           */
+#define VOFL_ERR_UNSUPPORTED -5 /* grid size without a compiled FFT length, or a
+                                   scheme not provided for the plan's model          */
 
 /* precision of the transforms and pointwise work; the expansion coefficients,
    the spectral multipliers, the propagator and the spectral state are FP64 in
@@ -85,6 +86,12 @@ typedef struct vofl_desc {
                             candidate tile/radix variant over this many steps on
                             temporary buffers and keeps the fastest (cached in the
                             file named by VOFL_TUNE_CACHE, when set)                 */
+    int order;           /* time splitting of vofl_step: 0 or 2: TSFP2 (3.13); 4: the
+                            higher-order splitting named after (3.13), built as the
+                            symmetric composition of three TSFP2 steps of lengths
+                            w1 dt, w0 dt, w1 dt (w1 = 1/(2 - 2^{1/3}), w0 = 1 - 2 w1);
+                            generic model only (its kick is exact), else
+                            VOFL_ERR_UNSUPPORTED                                       */
 } vofl_desc;
 
 typedef struct vofl_plan_s* vofl_plan_t;

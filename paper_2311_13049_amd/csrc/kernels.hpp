@@ -1062,7 +1062,16 @@ struct Args1D {
     double dt, invN;
     int* flag;
     double lf_cb, lf_ca, lf_cf;   // leap-frog first-step coefficients (k_1d_lffp)
+    // sub-steps per step (1: TSFP2; 3: the fourth-order composition with
+    // sub-step weights w1, w0, w1)
+    int sub;
+    double w1, w0;
 };
+
+// Length of sub-step k of a composed step (weights w1, w0, w1) or dt.
+__device__ __forceinline__ double substep_len(double dt, int sub, double w1, double w0, int k) {
+    return sub == 3 ? dt * ((k % 3 == 1) ? w0 : w1) : dt;
+}
 
 template <typename T, int N, int E>
 __global__ __launch_bounds__(N / E) void k_1d_apply(Args1D<T> a) {
@@ -1197,8 +1206,10 @@ __global__ __launch_bounds__(N / E) void k_1d_step(Args1D<T> a) {
         }
     };
     bool bad = false;
-    if (a.nsteps > 0) propagate(0.5 * a.dt);
-    for (int s = 0; s < a.nsteps; ++s) {
+    const int K = a.nsteps * a.sub;  // sub-steps
+    if (K > 0) propagate(0.5 * substep_len(a.dt, a.sub, a.w1, a.w0, 0));
+    for (int s = 0; s < K; ++s) {
+        const double ds = substep_len(a.dt, a.sub, a.w1, a.w0, s);
         double acc[E];
         if (a.model == MODEL_GENERIC) {
             // dv = -kappa sum_{s=1..M} delta^s t_s + lambda u^3, with t_s from
@@ -1299,10 +1310,10 @@ __global__ __launch_bounds__(N / E) void k_1d_step(Args1D<T> a) {
             z[e] = {T(acc[e]), T(0)};
         }
         fft_pencil<T, N, E, -1>(z, t, lds, tw_s);
-        const double sc2 = a.dt * a.invN;
+        const double sc2 = ds * a.invN;
 #pragma unroll
         for (int e = 0; e < E; ++e) vh[e] = {vh[e].x + sc2 * double(z[e].x), vh[e].y + sc2 * double(z[e].y)};
-        propagate(s + 1 < a.nsteps ? a.dt : 0.5 * a.dt);
+        propagate(s + 1 < K ? 0.5 * (ds + substep_len(a.dt, a.sub, a.w1, a.w0, s + 1)) : 0.5 * ds);
     }
     if (bad) a.flag[0] = 1;
     cpx<T> y[E];

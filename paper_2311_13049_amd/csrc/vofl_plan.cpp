@@ -100,6 +100,9 @@ int derive(const vofl_desc* d, Geometry& g) {
     if (d->coef_per_solve != 0 && d->coef_per_solve != 1)
         return fail(VOFL_ERR_INVALID, "coef_per_solve must be 0 or 1");
     if (d->tune_steps < 0 || d->tune_steps > 1000) return fail(VOFL_ERR_INVALID, "tune_steps must be in [0, 1000]");
+    if (d->order != 0 && d->order != 2 && d->order != 4) return fail(VOFL_ERR_INVALID, "order must be 2 or 4");
+    if (d->order == 4 && d->model != VOFL_MODEL_GENERIC)
+        return fail(VOFL_ERR_UNSUPPORTED, "the fourth-order composition is provided for the generic model (1.5)");
     g.batch = d->batch ? d->batch : 1;
     g.max_batch = d->max_batch ? d->max_batch : 1;
     g.ncoef = d->coef_per_solve ? g.batch : 1;
@@ -194,6 +197,8 @@ struct vofl_plan_s {
     cpx<double>* tw64[3] = {nullptr, nullptr, nullptr};
     double* delta = nullptr;
     double* LS = nullptr;              // leap-frog FP64 state: u^{n-1} of every solve, then u^n
+    int sub = 1;                       // sub-steps per step (3: fourth-order composition)
+    double w1 = 1.0, w0 = 1.0;         // composition weights
     void* A = nullptr;
     void* B = nullptr;
     SolveScalars* sc = nullptr;
@@ -523,6 +528,11 @@ int lffp_multi(vofl_plan_s* p, double cb0, double ca0, double cf0, int nsteps, h
 
 
 
+// length of sub-step k (dt for TSFP2; dt w1, dt w0, dt w1 for the composition)
+double substep_len_h(const vofl_plan_s* p, int k) {
+    return p->sub == 3 ? p->dt * ((k % 3 == 1) ? p->w0 : p->w1) : p->dt;
+}
+
 template <typename T>
 int step_multi(vofl_plan_s* p, T* u, T* v, int nsteps, hipStream_t s) {
     if (nsteps == 0) return VOFL_OK;
@@ -557,7 +567,7 @@ int step_multi(vofl_plan_s* p, T* u, T* v, int nsteps, hipStream_t s) {
         a.in_kind = IN_INIT;
         a.emit_kind = emit_terms;
         a.do_prop = 1;
-        a.tprop = 0.5 * p->dt;
+        a.tprop = 0.5 * substep_len_h(p, 0);
         e = p->timed("contig_init", s, [&] { return Launch<T>::contig(g.nlast, a, items, s); });
         if (e != hipSuccess) return hip_fail(e, "contig launch");
     }
@@ -577,14 +587,17 @@ int step_multi(vofl_plan_s* p, T* u, T* v, int nsteps, hipStream_t s) {
     a.in_kind = IN_KICK;
     a.do_prop = 1;
 
-    for (int st = 0; st < nsteps; ++st) {
-        const bool last = (st + 1 == nsteps);
+    const int K = nsteps * p->sub;  // sub-steps (TSFP2: one per step)
+    for (int st = 0; st < K; ++st) {
+        const bool last = (st + 1 == K);
+        const double ds = substep_len_h(p, st);
+        a.dt = ds;  // the kick of this sub-step
         if ((e = mid<T>(p, "mid_terms", +1, W, SS, nterm, items, twm, s)) != hipSuccess) return hip_fail(e, "mid launch");
         e = p->timed("c2r0_kick", s, [&] { return Launch<T>::c2r0(g.n[0], c, items, s, p->c2r_variant); });
         if (e != hipSuccess) return hip_fail(e, "c2r0 launch");
         if ((e = mid<T>(p, "mid_dv", -1, W + (long long)dv * g.H, SS, 1, items, twm, s)) != hipSuccess)
             return hip_fail(e, "mid launch");
-        a.tprop = last ? 0.5 * p->dt : p->dt;
+        a.tprop = last ? 0.5 * ds : 0.5 * (ds + substep_len_h(p, st + 1));
         a.emit_kind = last ? EMIT_EXPORT : emit_terms;
         a.out = W + (last ? (long long)h0 * g.H : 0);
         e = p->timed("contig_kick", s, [&] { return Launch<T>::contig(g.nlast, a, items, s); });
@@ -622,6 +635,9 @@ Args1D<T> args_1d(vofl_plan_s* p) {
     a.dt = p->dt;
     a.invN = 1.0 / (double)g.Nreal;
     a.flag = p->flag;
+    a.sub = p->sub;
+    a.w1 = p->w1;
+    a.w0 = p->w0;
     return a;
 }
 
@@ -880,6 +896,13 @@ int vofl_plan(const vofl_desc* d, void* stream, vofl_plan_t* out) {
         p->hi[i] = d->hi[i];
     }
     p->sc_host = sc;
+    if (d->order == 4) {
+        // fourth-order composition of three TSFP2 steps (symmetric triple jump)
+        const double c = std::cbrt(2.0);
+        p->sub = 3;
+        p->w1 = 1.0 / (2.0 - c);
+        p->w0 = -c / (2.0 - c);
+    }
     // default axis-0 kernel: the paired layout (each stored row loaded once)
     // where the length allows it
     if (g.ndim >= 2) {

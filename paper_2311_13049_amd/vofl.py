@@ -61,6 +61,7 @@ class vofl_desc(ctypes.Structure):
         ("coef_per_solve", ctypes.c_int),
         ("hbm_budget", ctypes.c_size_t),
         ("tune_steps", ctypes.c_int),
+        ("order", ctypes.c_int),
     ]
 
 
@@ -119,7 +120,7 @@ def _check(rc: int) -> int:
 
 def make_desc(shape, lo, hi, *, model="seismic", c0=1.0, omega0=1.0, Q=None, gamma=None,
               s=None, kappa=1.0, lam=0.0, M=8, dt=1e-3, precision="fp64", max_batch=1,
-              batch=1, coef_per_solve=False, hbm_budget=0, tune_steps=0):
+              batch=1, coef_per_solve=False, hbm_budget=0, tune_steps=0, order=2):
     """Build a vofl_desc; returns (desc, keepalive) where keepalive holds the host arrays."""
     shape = tuple(int(n) for n in shape)
     d = vofl_desc()
@@ -151,6 +152,7 @@ def make_desc(shape, lo, hi, *, model="seismic", c0=1.0, omega0=1.0, Q=None, gam
     d.coef_per_solve = 1 if coef_per_solve else 0
     d.hbm_budget = int(hbm_budget)
     d.tune_steps = int(tune_steps)
+    d.order = int(order)
     return d, keep
 
 

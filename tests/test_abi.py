@@ -70,6 +70,8 @@ def _rc(**kw):
     (dict(model="generic", gamma=None, s=np.full(512, 1.0), kappa=0.0), V.VOFL_ERR_INVALID),
     (dict(model="generic", gamma=None, s=None, kappa=1.0), V.VOFL_ERR_INVALID),
     (dict(batch=-2), V.VOFL_ERR_INVALID),
+    (dict(order=3), V.VOFL_ERR_INVALID),
+    (dict(order=4), V.VOFL_ERR_UNSUPPORTED),                                         # seismic model
 ])
 def test_descriptor_validation(kw, code):
     assert _rc(**kw) == code

@@ -233,3 +233,41 @@ def test_seismic_reflection_symmetry():
     idx = (-np.arange(J)) % J
     np.testing.assert_allclose(u, u[idx], atol=1e-13)
     np.testing.assert_allclose(v, v[idx], atol=1e-12)
+
+
+def test_fourth_order_composition_converges_at_order_four():
+    """The composed splitting (three TSFP2 steps w1, w0, w1) for (1.5) with
+    f = u^3 converges at fourth order to the semi-discrete solution."""
+    from oracle import tsfp4_generic
+    J, lo, hi = 32, -8.0, 8.0
+    x = grid_1d(J, lo, hi)
+    s = 1.0 + 0.3 * np.sin(np.pi * x / 8.0)
+    kap = 0.9
+    L = dense_matrix_1d(s, lo, hi)
+    u0 = np.exp(-x * x)
+    v0 = np.zeros(J)
+
+    def rhs(_, y):
+        u, v = y[:J], y[J:]
+        return np.concatenate([v, -kap * (L @ u) + u ** 3])
+    t = 0.5
+    ref = solve_ivp(rhs, (0, t), np.concatenate([u0, v0]), method="DOP853",
+                    rtol=1e-13, atol=1e-15).y[:J, -1]
+    errs = []
+    for steps in (10, 20, 40):
+        u, _ = tsfp4_generic(u0, v0, s, kap, (lo,), (hi,), 30, t / steps, steps, f=lambda u: u ** 3)
+        errs.append(np.linalg.norm(u - ref) / np.linalg.norm(ref))
+    rates = [np.log2(a / b) for a, b in zip(errs, errs[1:])]
+    assert all(3.7 < r < 4.4 for r in rates), (errs, rates)
+
+
+def test_fourth_order_composition_constant_order_linear_is_exact():
+    """Constant order, f = 0: every sub-step is exact (Remark 3.1), so is the composition."""
+    from oracle import tsfp4_generic
+    J, lo, hi = 64, (-8.0,), (8.0,)
+    x = grid_1d(J, lo[0], hi[0])
+    u0, v0 = np.exp(-x * x), 0.2 * np.sin(np.pi * x / 4)
+    a, va = tsfp4_generic(u0, v0, np.full(J, 1.2), 1.3, lo, hi, 5, 0.05, 7)
+    b, vb = tsfp2_generic(u0, v0, np.full(J, 1.2), 1.3, lo, hi, 5, 0.35, 1)
+    np.testing.assert_allclose(a, b, atol=1e-12)
+    np.testing.assert_allclose(va, vb, atol=1e-12)
