@@ -68,7 +68,7 @@ import numpy as np
 __all__ = [
     "fft_bins", "wavenumbers", "mu_squared", "gamma_from_Q",
     "seismic_coefficients", "dense_dft", "dense_apply", "dense_matrix_1d",
-    "mterm_apply", "seismic_op_order", "tsfp2_generic", "tsfp4_generic", "lffp_generic",
+    "mterm_apply", "seismic_op_order", "tsfp2_generic", "tsfp4_generic", "lffp_generic", "cnfp_generic",
     "damped_propagator",
     "tsfp2_seismic", "weighted_l2", "rel_l2", "mterm_apply_at", "set_fft_workers",
 ]
@@ -434,6 +434,74 @@ def lffp_generic(phi, psi, s, kappa: float, lo, hi, M: int, dt: float,
         cur = u + dt * np.asarray(psi, dtype=np.float64) + 0.5 * dt * dt * F(u)
         for _ in range(nsteps - 1):
             prev, cur = cur, 2.0 * cur - prev + dt * dt * F(cur)
+    return prev, cur
+
+
+def cnfp_generic(phi, psi, s, kappa: float, lo, hi, M: int, dt: float,
+                 nsteps: int, f=None, tol: float = 1e-14, max_outer: int = 100):
+    """Crank-Nicolson Fourier pseudospectral scheme (3.2) with the start (3.3)
+    for u_tt = -kappa (-Lap)^{s(x)} u + f(u), (2.13) as the operator L.
+
+    Each step solves for w = u^{n+1}:
+      w + a L w - b f(w) = 2 u^n - u^{n-1} - a L u^{n-1} + b f(u^{n-1}),
+    a = kappa dt^2/2, b = dt^2/2, by fixed-point iteration on f(w); every
+    linear solve with I + a L uses the library's GMRES, preconditioned by the
+    exact inverse of I + a (-Lap)^{s0} (a Fourier multiplier), to a relative
+    residual of tol. Returns (u^{nsteps-1}, u^{nsteps}).
+    """
+    from scipy.sparse.linalg import LinearOperator, gmres
+    u = np.asarray(phi, dtype=np.float64)
+    shape = u.shape
+    N = u.size
+    s = np.broadcast_to(np.asarray(s, dtype=np.float64), shape)
+    s0 = float(np.mean(s))
+    delta = s - s0
+    mu2 = mu_squared(shape, lo, hi)
+    nz = mu2 > 0.0
+    lnmu2 = np.zeros_like(mu2)
+    lnmu2[nz] = np.log(mu2[nz])
+    base = np.zeros_like(mu2)
+    base[nz] = mu2[nz] ** s0
+    # constant order: delta = 0, so only the m = 0 term is nonzero
+    nterms = M + 1 if np.any(delta != 0.0) else 1
+    coefs = [lnmu2 ** m / math.factorial(m) * base for m in range(nterms)]
+    dpow = [delta ** m for m in range(nterms)]
+
+    def L(w):
+        wh = _to_spec(w)
+        out = np.zeros(shape)
+        for m in range(nterms):
+            out += dpow[m] * _to_phys(coefs[m] * wh)
+        return out
+
+    def fv(w):
+        return f(w) if f is not None else np.zeros(shape)
+
+    a = kappa * dt * dt / 2.0
+    b = dt * dt / 2.0
+    A = LinearOperator((N, N), matvec=lambda x: (x.reshape(shape) + a * L(x.reshape(shape))).ravel(),
+                       dtype=np.float64)
+    inv0 = 1.0 / (1.0 + a * base)
+    P = LinearOperator((N, N), matvec=lambda x: _to_phys(inv0 * _to_spec(x.reshape(shape))).ravel(),
+                       dtype=np.float64)
+    if nsteps == 0:
+        return u.copy(), u.copy()
+    prev = u
+    cur = u + dt * np.asarray(psi, dtype=np.float64) + b * (-kappa * L(u) + fv(u))
+    for _ in range(nsteps - 1):
+        r = 2.0 * cur - prev - a * L(prev) + b * fv(prev)
+        w = 2.0 * cur - prev
+        for _ in range(max_outer):
+            rhs = r + b * fv(w)
+            x, info = gmres(A, rhs.ravel(), x0=w.ravel(), rtol=tol, atol=0.0, restart=50, maxiter=200, M=P)
+            if info != 0:
+                raise RuntimeError(f"GMRES did not converge (info {info})")
+            wn = x.reshape(shape)
+            done = np.linalg.norm(wn - w) <= tol * max(np.linalg.norm(wn), 1e-300)
+            w = wn
+            if done:
+                break
+        prev, cur = cur, w
     return prev, cur
 
 
