@@ -1451,4 +1451,78 @@ __global__ __launch_bounds__(N / E) void k_1d_lffp(Args1D<T> a) {
     }
 }
 
+// ---------------------------------------------------------------------------
+// vector kernels of the Crank-Nicolson solver (plan precision vectors,
+// FP64 arithmetic and FP64 dot products)
+// ---------------------------------------------------------------------------
+// out = c0 x0 + c1 x1 + c2 x2 + cq xq^3 (a null input is skipped; out may
+// alias an input: each element is read before it is written by its thread)
+template <typename T>
+__global__ __launch_bounds__(256) void k_lincomb(T* out, const T* x0, double c0, const T* x1, double c1,
+                                                 const T* x2, double c2, const T* xq, double cq, long long n) {
+    for (long long i = blockIdx.x * 256LL + threadIdx.x; i < n; i += (long long)gridDim.x * 256LL) {
+        double r = 0.0;
+        if (x0) r += c0 * double(x0[i]);
+        if (x1) r += c1 * double(x1[i]);
+        if (x2) r += c2 * double(x2[i]);
+        if (xq) {
+            const double q = double(xq[i]);
+            r += cq * q * q * q;
+        }
+        out[i] = T(r);
+    }
+}
+
+// Partial sums of a0.b0 and a1.b1 (a1 may be null): one pair per workgroup,
+// over a fixed grid, so the summation order does not depend on timing.
+template <typename T>
+__global__ __launch_bounds__(256) void k_dot2(const T* a0, const T* b0, const T* a1, const T* b1, long long n,
+                                              double* partial) {
+    __shared__ double red[2][256];
+    double s0 = 0.0, s1 = 0.0;
+    for (long long i = blockIdx.x * 256LL + threadIdx.x; i < n; i += (long long)gridDim.x * 256LL) {
+        s0 += double(a0[i]) * double(b0[i]);
+        if (a1) s1 += double(a1[i]) * double(b1[i]);
+    }
+    red[0][threadIdx.x] = s0;
+    red[1][threadIdx.x] = s1;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if (threadIdx.x < w) {
+            red[0][threadIdx.x] += red[0][threadIdx.x + w];
+            red[1][threadIdx.x] += red[1][threadIdx.x + w];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        partial[2 * blockIdx.x] = red[0][0];
+        partial[2 * blockIdx.x + 1] = red[1][0];
+    }
+}
+
+// out[0..1] = sums of the nb partial pairs (one workgroup)
+template <typename T>
+__global__ __launch_bounds__(256) void k_dot2_finish(const double* partial, int nb, double* out) {
+    __shared__ double red[2][256];
+    double s0 = 0.0, s1 = 0.0;
+    for (int b = threadIdx.x; b < nb; b += 256) {
+        s0 += partial[2 * b];
+        s1 += partial[2 * b + 1];
+    }
+    red[0][threadIdx.x] = s0;
+    red[1][threadIdx.x] = s1;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if (threadIdx.x < w) {
+            red[0][threadIdx.x] += red[0][threadIdx.x + w];
+            red[1][threadIdx.x] += red[1][threadIdx.x + w];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        out[0] = red[0][0];
+        out[1] = red[1][0];
+    }
+}
+
 }  // namespace vofl

@@ -47,6 +47,13 @@ struct Launch {
     // element-wise T <-> FP64 copies of n values
     static hipError_t to_f64(const T* in, double* out, long long n, hipStream_t s);
     static hipError_t from_f64(const double* in, T* out, long long n, hipStream_t s);
+    // Crank-Nicolson vector kernels (see k_lincomb, k_dot2); dot2 leaves the
+    // two sums in out[0], out[1] (device) using partial[2 * dot_blocks]
+    static constexpr int dot_blocks = 512;
+    static hipError_t lincomb(T* out, const T* x0, double c0, const T* x1, double c1, const T* x2, double c2,
+                              const T* xq, double cq, long long n, hipStream_t s);
+    static hipError_t dot2(const T* a0, const T* b0, const T* a1, const T* b1, long long n, double* partial,
+                           double* out, hipStream_t s);
 };
 
 extern template struct Launch<float>;

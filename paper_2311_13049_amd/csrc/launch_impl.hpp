@@ -303,4 +303,19 @@ hipError_t Launch<T>::from_f64(const double* in, T* out, long long n, hipStream_
     return hipGetLastError();
 }
 
+template <typename T>
+hipError_t Launch<T>::lincomb(T* out, const T* x0, double c0, const T* x1, double c1, const T* x2, double c2,
+                              const T* xq, double cq, long long n, hipStream_t s) {
+    k_lincomb<T><<<dim3(convert_blocks(n)), dim3(256), 0, s>>>(out, x0, c0, x1, c1, x2, c2, xq, cq, n);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t Launch<T>::dot2(const T* a0, const T* b0, const T* a1, const T* b1, long long n, double* partial,
+                           double* out, hipStream_t s) {
+    k_dot2<T><<<dim3(dot_blocks), dim3(256), 0, s>>>(a0, b0, a1, b1, n, partial);
+    k_dot2_finish<T><<<dim3(1), dim3(256), 0, s>>>(partial, dot_blocks, out);
+    return hipGetLastError();
+}
+
 }  // namespace vofl

@@ -49,6 +49,11 @@ int hip_fail(hipError_t e, const char* what) {
 }
 
 // Sizes derived from a validated descriptor (no device access).
+// Crank-Nicolson solver storage (generic model, batch 1): vectors of N
+// values in the plan precision and FP64 reduction scalars
+constexpr int CN_VECTORS = 11;
+constexpr int CN_SCALARS = 2 * 512 + 8;
+
 struct Geometry {
     int ndim = 0;
     int n[3] = {1, 1, 1};
@@ -162,6 +167,8 @@ int derive(const vofl_desc* d, Geometry& g) {
         if (d->model == VOFL_MODEL_GENERIC)
             bytes += (size_t)2 * g.batch * g.Nreal * 8;        // FP64 leap-frog state (u^{n-1}, u^n)
     }
+    if (d->model == VOFL_MODEL_GENERIC && g.batch == 1)
+        bytes += (size_t)CN_VECTORS * g.Nreal * g.elt + CN_SCALARS * 8;  // Crank-Nicolson solver vectors
     g.bytes = bytes;
     if (d->hbm_budget && bytes > d->hbm_budget)
         return fail(VOFL_ERR_NOMEM, "plan needs %zu bytes, above hbm_budget %zu", bytes, d->hbm_budget);
@@ -197,6 +204,8 @@ struct vofl_plan_s {
     cpx<double>* tw64[3] = {nullptr, nullptr, nullptr};
     double* delta = nullptr;
     double* LS = nullptr;              // leap-frog FP64 state: u^{n-1} of every solve, then u^n
+    void* cnv = nullptr;               // Crank-Nicolson vectors (CN_VECTORS x N)
+    double* cns = nullptr;             // Crank-Nicolson reduction scalars
     int sub = 1;                       // sub-steps per step (3: fourth-order composition)
     double w1 = 1.0, w0 = 1.0;         // composition weights
     void* A = nullptr;
@@ -376,6 +385,10 @@ int upload_tables(vofl_plan_s* p, const std::vector<double>& delta, const std::v
         if (p->model == VOFL_MODEL_GENERIC &&
             (rc = dalloc(p, &p->LS, (size_t)2 * g.batch * g.Nreal * sizeof(double))))
             return rc;
+    }
+    if (p->model == VOFL_MODEL_GENERIC && g.batch == 1) {
+        if ((rc = dalloc(p, (T**)&p->cnv, (size_t)CN_VECTORS * g.Nreal * sizeof(T)))) return rc;
+        if ((rc = dalloc(p, &p->cns, (size_t)CN_SCALARS * sizeof(double)))) return rc;
     }
     return VOFL_OK;
 }
@@ -672,6 +685,7 @@ int lffp_any(vofl_plan_s* p, const void* cur_in, const void* prev_in, void* cur_
     return e == hipSuccess ? VOFL_OK : hip_fail(e, "state store");
 }
 
+
 template <typename T>
 int apply_any(vofl_plan_s* p, int op, const void* u, void* out, int nf, hipStream_t s) {
     if (p->g.ndim >= 2) return apply_multi<T>(p, op, (const T*)u, (T*)out, nf, s);
@@ -681,6 +695,111 @@ int apply_any(vofl_plan_s* p, int op, const void* u, void* out, int nf, hipStrea
     a.op = op;
     hipError_t e = p->timed("1d_apply", s, [&] { return Launch<T>::d1_apply(a.N, a, nf, s); });
     if (e != hipSuccess) return hip_fail(e, "1d apply launch");
+    return VOFL_OK;
+}
+
+// Crank-Nicolson scheme (3.2) for the generic model, batch 1: per step,
+// w = u^{n+1} solves w + a L w - b f(w) = r with
+// r = 2 u^n - u^{n-1} - a L u^{n-1} + b f(u^{n-1}), a = kappa dt^2/2,
+// b = dt^2/2, f(w) = lambda w^3; fixed-point iteration on f(w), each linear
+// solve with I + a L by BiCGSTAB (the operator (2.13) is not symmetric).
+// Host-driven: the scalars of every iteration are read back.
+template <typename T>
+int cnfp_run(vofl_plan_s* p, T* up, T* u, int nsteps, double tol, int max_iter, long long* iters,
+             hipStream_t s) {
+    const long long n = p->g.Nreal;
+    T* V = (T*)p->cnv;
+    T *r = V, *w = V + n, *x = V + 2 * n, *b = V + 3 * n, *res = V + 4 * n, *rh = V + 5 * n, *pv = V + 6 * n,
+      *vv = V + 7 * n, *sv = V + 8 * n, *tv = V + 9 * n, *lw = V + 10 * n;
+    double* part = p->cns;
+    double* dres = p->cns + 2 * Launch<T>::dot_blocks;
+    const SolveScalars sc = p->sc_host[0];
+    const double kap = sc.kappa0, lam = sc.lambda;
+    const double a = 0.5 * kap * p->dt * p->dt, bb = 0.5 * p->dt * p->dt;
+    hipError_t e = hipSuccess;
+    auto chk = [&](hipError_t ee) { if (e == hipSuccess) e = ee; };
+    auto L = [&](const T* in, T* out) { return apply_any<T>(p, VOFL_OP_S1, in, out, 1, s); };
+    // (I + a L) in -> out, with lw as scratch
+    auto A = [&](const T* in, T* out) {
+        int rc = L(in, lw);
+        if (rc) return rc;
+        chk(Launch<T>::lincomb(out, in, 1.0, lw, a, nullptr, 0.0, nullptr, 0.0, n, s));
+        return e == hipSuccess ? VOFL_OK : hip_fail(e, "lincomb");
+    };
+    double host2[2];
+    auto dot2 = [&](const T* a0, const T* b0, const T* a1, const T* b1) -> int {
+        chk(Launch<T>::dot2(a0, b0, a1, b1, n, part, dres, s));
+        if (e == hipSuccess) chk(hipMemcpyAsync(host2, dres, 2 * sizeof(double), hipMemcpyDeviceToHost, s));
+        if (e == hipSuccess) chk(hipStreamSynchronize(s));
+        return e == hipSuccess ? VOFL_OK : hip_fail(e, "dot product");
+    };
+    long long total = 0;
+    int rc;
+    for (int step = 0; step < nsteps; ++step) {
+        // r = 2u - up - a L up + b lambda up^3
+        if ((rc = L(up, lw))) return rc;
+        chk(Launch<T>::lincomb(r, u, 2.0, up, -1.0, lw, -a, up, bb * lam, n, s));
+        chk(Launch<T>::lincomb(w, u, 2.0, up, -1.0, nullptr, 0.0, nullptr, 0.0, n, s));
+        if (e != hipSuccess) return hip_fail(e, "lincomb");
+        bool outer_done = false;
+        for (int outer = 0; outer < 100 && !outer_done; ++outer) {
+            // b = r + b lambda w^3; x0 = w
+            chk(Launch<T>::lincomb(b, r, 1.0, nullptr, 0.0, nullptr, 0.0, w, bb * lam, n, s));
+            chk(Launch<T>::lincomb(x, w, 1.0, nullptr, 0.0, nullptr, 0.0, nullptr, 0.0, n, s));
+            if ((rc = A(x, res))) return rc;
+            chk(Launch<T>::lincomb(res, b, 1.0, res, -1.0, nullptr, 0.0, nullptr, 0.0, n, s));
+            chk(Launch<T>::lincomb(rh, res, 1.0, nullptr, 0.0, nullptr, 0.0, nullptr, 0.0, n, s));
+            if ((rc = dot2(b, b, res, res))) return rc;
+            const double bnorm = std::sqrt(host2[0]);
+            double rr = host2[1];
+            double rho = 1.0, alpha = 1.0, omega = 1.0;
+            bool conv = std::sqrt(rr) <= tol * bnorm;
+            for (int it = 0; it < max_iter && !conv; ++it) {
+                ++total;
+                if ((rc = dot2(rh, res, nullptr, nullptr))) return rc;
+                const double rho_new = host2[0];
+                if (it == 0) {
+                    chk(Launch<T>::lincomb(pv, res, 1.0, nullptr, 0.0, nullptr, 0.0, nullptr, 0.0, n, s));
+                } else {
+                    const double beta = (rho_new / rho) * (alpha / omega);
+                    // p = r + beta (p - omega v)
+                    chk(Launch<T>::lincomb(pv, res, 1.0, pv, beta, vv, -beta * omega, nullptr, 0.0, n, s));
+                }
+                rho = rho_new;
+                if ((rc = A(pv, vv))) return rc;
+                if ((rc = dot2(rh, vv, nullptr, nullptr))) return rc;
+                alpha = rho / host2[0];
+                chk(Launch<T>::lincomb(sv, res, 1.0, vv, -alpha, nullptr, 0.0, nullptr, 0.0, n, s));
+                if ((rc = dot2(sv, sv, nullptr, nullptr))) return rc;
+                if (std::sqrt(host2[0]) <= tol * bnorm) {
+                    chk(Launch<T>::lincomb(x, x, 1.0, pv, alpha, nullptr, 0.0, nullptr, 0.0, n, s));
+                    conv = true;
+                    break;
+                }
+                if ((rc = A(sv, tv))) return rc;
+                if ((rc = dot2(tv, sv, tv, tv))) return rc;
+                omega = host2[0] / host2[1];
+                chk(Launch<T>::lincomb(x, x, 1.0, pv, alpha, sv, omega, nullptr, 0.0, n, s));
+                chk(Launch<T>::lincomb(res, sv, 1.0, tv, -omega, nullptr, 0.0, nullptr, 0.0, n, s));
+                if ((rc = dot2(res, res, nullptr, nullptr))) return rc;
+                if (!std::isfinite(host2[0])) break;
+                conv = std::sqrt(host2[0]) <= tol * bnorm;
+            }
+            if (!conv) return fail(VOFL_ERR_UNSTABLE, "BiCGSTAB did not reach the tolerance in %d iterations", max_iter);
+            // fixed point on f(w): stop when the iterate no longer moves
+            chk(Launch<T>::lincomb(lw, x, 1.0, w, -1.0, nullptr, 0.0, nullptr, 0.0, n, s));
+            if ((rc = dot2(lw, lw, x, x))) return rc;
+            outer_done = std::sqrt(host2[0]) <= tol * std::sqrt(host2[1]) || lam == 0.0;
+            chk(Launch<T>::lincomb(w, x, 1.0, nullptr, 0.0, nullptr, 0.0, nullptr, 0.0, n, s));
+            if (e != hipSuccess) return hip_fail(e, "lincomb");
+        }
+        if (!outer_done) return fail(VOFL_ERR_UNSTABLE, "fixed-point iteration on f(u) did not converge");
+        // (up, u) <- (u, w)
+        chk(Launch<T>::lincomb(up, u, 1.0, nullptr, 0.0, nullptr, 0.0, nullptr, 0.0, n, s));
+        chk(Launch<T>::lincomb(u, w, 1.0, nullptr, 0.0, nullptr, 0.0, nullptr, 0.0, n, s));
+        if (e != hipSuccess) return hip_fail(e, "lincomb");
+    }
+    if (iters) *iters = total;
     return VOFL_OK;
 }
 
@@ -1040,6 +1159,24 @@ int vofl_lffp_step(vofl_plan_t p, void* u_prev, void* u, int nsteps, void* strea
     const double dt2 = p->dt * p->dt;
     return p->precision == VOFL_FP32 ? lffp_any<float>(p, u, u_prev, u, u_prev, 2.0, -1.0, dt2, nsteps, s)
                                      : lffp_any<double>(p, u, u_prev, u, u_prev, 2.0, -1.0, dt2, nsteps, s);
+}
+
+int vofl_cnfp_step(vofl_plan_t p, void* u_prev, void* u, int nsteps, double tol, int max_iter,
+                   long long* iterations, void* stream) {
+    if (!p) return fail(VOFL_ERR_INVALID, "plan is NULL");
+    if (!u_prev || !u) return fail(VOFL_ERR_INVALID, "u_prev and u must be device pointers");
+    if (u_prev == u) return fail(VOFL_ERR_INVALID, "u_prev and u must be distinct");
+    if (nsteps < 0) return fail(VOFL_ERR_INVALID, "nsteps must be >= 0");
+    if (!(tol > 0.0 && tol < 1.0)) return fail(VOFL_ERR_INVALID, "tol must be in (0, 1)");
+    if (max_iter < 1) return fail(VOFL_ERR_INVALID, "max_iter must be >= 1");
+    if (p->model != VOFL_MODEL_GENERIC || p->g.batch != 1)
+        return fail(VOFL_ERR_UNSUPPORTED, "the Crank-Nicolson scheme is provided for the generic model (1.5) with batch 1");
+    if (iterations) *iterations = 0;
+    if (nsteps == 0) return VOFL_OK;
+    hipStream_t s = (hipStream_t)stream;
+    return p->precision == VOFL_FP32
+               ? cnfp_run<float>(p, (float*)u_prev, (float*)u, nsteps, tol, max_iter, iterations, s)
+               : cnfp_run<double>(p, (double*)u_prev, (double*)u, nsteps, tol, max_iter, iterations, s);
 }
 
 int vofl_step_batch(vofl_plan_t* plans, void** u, void** v, const int* nsteps, int count, void* stream) {

@@ -32,7 +32,7 @@ VOFL_OP_S2 = 2
 # every function declared in include/vofl.h
 ABI_FUNCTIONS = (
     "vofl_plan", "vofl_plan_footprint", "vofl_apply", "vofl_step", "vofl_step_graph", "vofl_solve",
-    "vofl_lffp_start", "vofl_lffp_step", "vofl_step_batch", "vofl_sync_status", "vofl_set_timing", "vofl_kernel_times",
+    "vofl_lffp_start", "vofl_lffp_step", "vofl_cnfp_step", "vofl_step_batch", "vofl_sync_status", "vofl_set_timing", "vofl_kernel_times",
     "vofl_plan_info", "vofl_destroy", "vofl_last_error", "vofl_version",
 )
 
@@ -91,6 +91,8 @@ def load_library():
     lib.vofl_step_graph.argtypes = [vp, vp, vp, ctypes.c_int, vp]
     lib.vofl_lffp_start.argtypes = [vp, vp, vp, vp, vp, vp]
     lib.vofl_lffp_step.argtypes = [vp, vp, vp, ctypes.c_int, vp]
+    lib.vofl_cnfp_step.argtypes = [vp, vp, vp, ctypes.c_int, ctypes.c_double, ctypes.c_int,
+                                   ctypes.POINTER(ctypes.c_longlong), vp]
     lib.vofl_solve.argtypes = [vp, vp, vp, ctypes.c_int, vp, vp, vp]
     lib.vofl_step_batch.argtypes = [ctypes.POINTER(vp), ctypes.POINTER(vp), ctypes.POINTER(vp),
                                     ctypes.POINTER(ctypes.c_int), ctypes.c_int, vp]
@@ -103,7 +105,7 @@ def load_library():
     lib.vofl_last_error.restype = ctypes.c_char_p
     lib.vofl_version.restype = ctypes.c_char_p
     for name in ("vofl_plan", "vofl_plan_footprint", "vofl_apply", "vofl_step", "vofl_step_graph", "vofl_solve",
-                 "vofl_lffp_start", "vofl_lffp_step",
+                 "vofl_lffp_start", "vofl_lffp_step", "vofl_cnfp_step",
                  "vofl_step_batch", "vofl_sync_status", "vofl_set_timing", "vofl_kernel_times",
                  "vofl_plan_info", "vofl_destroy"):
         getattr(lib, name).restype = ctypes.c_int
@@ -194,6 +196,15 @@ def vofl_lffp_start(plan: int, phi_ptr: int, psi_ptr: int, u_prev_ptr: int, u_pt
 def vofl_lffp_step(plan: int, u_prev_ptr: int, u_ptr: int, nsteps: int, stream=0) -> None:
     _check(load_library().vofl_lffp_step(ctypes.c_void_p(plan), ctypes.c_void_p(u_prev_ptr),
                                          ctypes.c_void_p(u_ptr), nsteps, ctypes.c_void_p(stream)))
+
+
+def vofl_cnfp_step(plan: int, u_prev_ptr: int, u_ptr: int, nsteps: int, tol: float, max_iter: int,
+                   stream=0) -> int:
+    it = ctypes.c_longlong(0)
+    _check(load_library().vofl_cnfp_step(ctypes.c_void_p(plan), ctypes.c_void_p(u_prev_ptr),
+                                         ctypes.c_void_p(u_ptr), nsteps, float(tol), int(max_iter),
+                                         ctypes.byref(it), ctypes.c_void_p(stream)))
+    return it.value
 
 
 def vofl_solve(plan: int, u0_ptr: int, v0_ptr: int, nsteps: int, u_ptr: int, v_ptr: int,
@@ -318,6 +329,13 @@ class Plan:
         self._check_tensor(u, self.batch, "u")
         vofl_lffp_step(self.handle, u_prev.data_ptr(), u.data_ptr(), int(nsteps), self._stream())
         return u_prev, u
+
+    def cnfp_step(self, u_prev, u, nsteps: int, tol: float = 1e-13, max_iter: int = 200) -> int:
+        """Crank-Nicolson steps (3.2) in place; returns the BiCGSTAB iterations."""
+        self._check_tensor(u_prev, self.batch, "u_prev")
+        self._check_tensor(u, self.batch, "u")
+        return vofl_cnfp_step(self.handle, u_prev.data_ptr(), u.data_ptr(), int(nsteps), tol, max_iter,
+                              self._stream())
 
     def solve(self, u0, v0, nsteps: int):
         u = u0.clone()

@@ -93,6 +93,7 @@ def test_valid_descriptors_and_footprint_formula():
     b = V.vofl_plan_footprint(d)
     slots = max((M + 2) + 3, 3 * (M + 1))
     expect = (n0 + n1) * (8 + 16 + 8) + 512 * (8 + 8) + 64 + 256 + slots * H * 8 + max(2, 3) * H * 16 + 2 * 512 * 8
+    expect += 11 * 512 * 4 + (2 * 512 + 8) * 8   # Crank-Nicolson vectors (batch 1) and scalars
     assert b == expect
 
 
@@ -102,6 +103,7 @@ def test_null_plan_arguments_are_rejected():
     assert lib.vofl_step(None, None, None, 1, None) == V.VOFL_ERR_INVALID
     assert lib.vofl_lffp_step(None, None, None, 1, None) == V.VOFL_ERR_INVALID
     assert lib.vofl_lffp_start(None, None, None, None, None, None) == V.VOFL_ERR_INVALID
+    assert lib.vofl_cnfp_step(None, None, None, 1, 1e-12, 10, None, None) == V.VOFL_ERR_INVALID
     assert lib.vofl_destroy(None) == V.VOFL_ERR_INVALID
     assert "NULL" in V.vofl_last_error()
 
