@@ -40,6 +40,13 @@ Functions and what pins each one (tests/test_oracle_*.py):
   damped_propagator   exact solution of the constant-coefficient part of the
                       split seismic model. Pinned: matrix exponential of the
                       mode ODE; semigroup property.
+  lffp_seismic        leap-frog (3.4) for (1.1) (reading: backward difference
+                      in the damping term, Taylor start). Pinned: gamma = 0 is
+                      the classical leap-frog (closed-form cos(n theta) per
+                      mode); constant gamma follows the closed-form roots of
+                      the per-mode two-term recurrence; variable gamma and a
+                      layered c0 converge at first order to a high-order ODE
+                      integration of the semi-discrete system.
   tsfp2_seismic       TSFP2 extended to the viscoacoustic model (1.1) (reading
                       below). Pinned: gamma = 0 reduces to d'Alembert's
                       solution of the acoustic wave equation; constant gamma
@@ -69,7 +76,7 @@ __all__ = [
     "fft_bins", "wavenumbers", "mu_squared", "gamma_from_Q",
     "seismic_coefficients", "dense_dft", "dense_apply", "dense_matrix_1d",
     "mterm_apply", "seismic_op_order", "tsfp2_generic", "tsfp4_generic", "lffp_generic", "cnfp_generic",
-    "damped_propagator",
+    "damped_propagator", "lffp_seismic",
     "tsfp2_seismic", "weighted_l2", "rel_l2", "mterm_apply_at", "set_fft_workers",
 ]
 
@@ -541,6 +548,10 @@ def tsfp2_seismic(u0, v0, gamma, c0: float, omega0: float, lo, hi, M: int,
                   dt: float, nsteps: int):
     """TSFP2 for (1.1), steps taken one by one in physical/spectral form.
 
+    c0 is a number or a field of per-point phase velocities (a layered
+    medium); A and B are formed point by point, and the exact part uses
+    kappa0 = A(gbar, cbar), beta0 = B(gbar, cbar) with cbar the grid mean of c0.
+
     Per step: exact part over dt/2, kick, exact part over dt/2, where the kick is
       v <- v + dt [(kappa0 - A) t1_0 - A sum_{m>=1} delta^m t1_m
                    + (beta0 - B) t2_0 - B sum_{m>=1} delta^m t2_m],
@@ -553,8 +564,10 @@ def tsfp2_seismic(u0, v0, gamma, c0: float, omega0: float, lo, hi, M: int,
     gamma = np.broadcast_to(np.asarray(gamma, dtype=np.float64), u.shape)
     gbar = float(np.mean(gamma))
     delta = gamma - gbar
+    c0 = np.broadcast_to(np.asarray(c0, dtype=np.float64), u.shape)
     A, B = seismic_coefficients(gamma, c0, omega0)
-    kappa0, beta0 = (float(x) for x in seismic_coefficients(gbar, c0, omega0))
+    # exact part: coefficients at the mean order and the mean phase velocity
+    kappa0, beta0 = (float(x) for x in seismic_coefficients(gbar, float(np.mean(c0)), omega0))
     mu2 = mu_squared(u.shape, lo, hi)
     nz = mu2 > 0.0
     lnmu2 = np.zeros_like(mu2)
@@ -589,6 +602,60 @@ def tsfp2_seismic(u0, v0, gamma, c0: float, omega0: float, lo, hi, M: int,
             v2 = v1 + dt * dv
             uh, vh = exact_part(_to_spec(u1), _to_spec(v2))
     return _to_phys(uh), _to_phys(vh)
+
+
+def lffp_seismic(phi, psi, gamma, c0, omega0: float, lo, hi, M: int, dt: float,
+                 nsteps: int):
+    """Leap-frog scheme (3.4) carried over to the viscoacoustic model (1.1)
+    (the scheme of Example 3; the paper does not write it out, reading below).
+
+    With A = -c^2 eta and B = -c^2 tau (seismic_coefficients; c0 may be a
+    field of per-point phase velocities), (1.1) reads
+    u_tt = -A L1 u - B L2 u_t, L1 = (-Lap)^{1+gamma(x)}, L2 = (-Lap)^{1/2+gamma(x)},
+    both by the M-term expansion (2.13) about their grid-mean orders. The
+    time derivative inside the damping term is the backward difference
+    (u^n - u^{n-1})/dt, which keeps the scheme explicit; the start is the
+    Taylor step of (3.4c) with u_t(0) = psi:
+      u^1     = phi + dt psi + dt^2/2 (-A L1 phi - B L2 psi),
+      u^{n+1} = 2 u^n - u^{n-1} + dt^2 (-A L1 u^n - B L2 (u^n - u^{n-1})/dt).
+    Returns (u^{nsteps-1}, u^{nsteps}) (both phi for nsteps = 0).
+    """
+    u = np.asarray(phi, dtype=np.float64)
+    gamma = np.broadcast_to(np.asarray(gamma, dtype=np.float64), u.shape)
+    c0 = np.broadcast_to(np.asarray(c0, dtype=np.float64), u.shape)
+    gbar = float(np.mean(gamma))
+    delta = gamma - gbar
+    A, B = seismic_coefficients(gamma, c0, omega0)
+    mu2 = mu_squared(u.shape, lo, hi)
+    nz = mu2 > 0.0
+    lnmu2 = np.zeros_like(mu2)
+    lnmu2[nz] = np.log(mu2[nz])
+    P1 = np.zeros_like(mu2)
+    P2 = np.zeros_like(mu2)
+    P1[nz] = mu2[nz] ** (1.0 + gbar)
+    P2[nz] = mu2[nz] ** (0.5 + gbar)
+    c1 = [lnmu2 ** m / math.factorial(m) * P1 for m in range(M + 1)]
+    c2 = [lnmu2 ** m / math.factorial(m) * P2 for m in range(M + 1)]
+    dpow = [delta ** m for m in range(M + 1)]
+
+    def op(w, cm):
+        wh = _to_spec(w)
+        out = np.zeros(w.shape)
+        for m in range(M + 1):
+            out += dpow[m] * _to_phys(cm[m] * wh)
+        return out
+
+    def F(w, wt):
+        return -A * op(w, c1) - B * op(wt, c2)
+
+    if nsteps == 0:
+        return u.copy(), u.copy()
+    with np.errstate(all="ignore"):
+        prev = u
+        cur = u + dt * np.asarray(psi, dtype=np.float64) + 0.5 * dt * dt * F(u, np.asarray(psi, dtype=np.float64))
+        for _ in range(nsteps - 1):
+            prev, cur = cur, 2.0 * cur - prev + dt * dt * F(cur, (cur - prev) / dt)
+    return prev, cur
 
 
 # ---------------------------------------------------------------------------
