@@ -92,6 +92,11 @@ typedef struct vofl_desc {
                             w1 dt, w0 dt, w1 dt (w1 = 1/(2 - 2^{1/3}), w0 = 1 - 2 w1);
                             generic model only (its kick is exact), else
                             VOFL_ERR_UNSUPPORTED                                       */
+    const double* c0_field; /* seismic: host, per-point phase velocity c0(x) > 0 (N values,
+                            or batch * N with coef_per_solve = 1) for layered media, as
+                            in Example 3 (Section 4); A(x), B(x) then use c0(x), the
+                            exact part of vofl_step uses the grid mean of c0(x), and
+                            the scalar c0 is ignored. NULL: c0 everywhere             */
 } vofl_desc;
 
 typedef struct vofl_plan_s* vofl_plan_t;
@@ -132,14 +137,17 @@ int vofl_step(vofl_plan_t plan, void* u, void* v, int nsteps, void* stream);
 int vofl_solve(vofl_plan_t plan, const void* u0, const void* v0, int nsteps,
                void* u, void* v, void* stream);
 
-/* Leap-frog Fourier pseudospectral scheme LFFP (eq. (3.4)) for the generic
- * model (1.5): u^{n+1} = 2 u^n - u^{n-1} + dt^2 (-kappa L u^n + lambda
- * (u^n)^3), with L the M-term operator (2.13) of the plan's s(x). Plans of
- * the seismic model return VOFL_ERR_UNSUPPORTED (the paper defines the
- * scheme for (1.5)).
+/* Leap-frog Fourier pseudospectral scheme LFFP (eq. (3.4)).
+ * Generic model (1.5): u^{n+1} = 2 u^n - u^{n-1} + dt^2 F(u^n) with
+ * F(u) = -kappa L u + lambda u^3, L the M-term operator (2.13) of s(x).
+ * Seismic model (1.1), the scheme of Example 3 (Section 4): with
+ * w^n = (u^n - u^{n-1})/dt standing for u_t in the damping term,
+ * u^{n+1} = 2 u^n - u^{n-1} + dt^2 (-A L1 u^n - B L2 w^n), L1, L2 the M-term
+ * operators of orders 1+gamma(x), 1/2+gamma(x) (first order in dt through
+ * the damping term, second order when gamma = 0).
  *
  * vofl_lffp_start: the start (3.4b, c): u_prev = phi and
- * u = phi + dt psi + dt^2/2 (-kappa L phi + lambda phi^3).
+ * u = phi + dt psi + dt^2/2 F(phi) (seismic: F(phi) = -A L1 phi - B L2 psi).
  * vofl_lffp_step: nsteps >= 0 steps on (u_prev, u) = (u^{n-1}, u^n), in
  * place; on return they hold (u^{n+nsteps-1}, u^{n+nsteps}).
  * All fields: device, batch * N values each, plan precision; u_prev != u

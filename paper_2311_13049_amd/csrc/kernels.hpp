@@ -450,10 +450,13 @@ struct C2RArgs {
     T* r1;                  // export: v
     long long Nreal;
     int* flag;              // set to 1 on a non-finite kick value
-    // leap-frog (apply mode with lffp = 1): FP64 fields of item b at
-    // s_prev + b*Nreal, s_cur + b*Nreal; per point
-    //   new = lf_cb*cur + lf_ca*prev + lf_cf*(-kappa acc + lambda cur^3),
-    //   prev <- cur, cur <- new (acc = the operator (2.13) applied to cur)
+    // leap-frog (lffp = 1): FP64 fields of item b at s_prev + b*Nreal,
+    // s_cur + b*Nreal; per point prev <- cur, cur <- new with
+    //   apply mode (1.5): new = lf_cb*cur + lf_ca*prev + lf_cf*(-kappa acc + lambda cur^3),
+    //     acc = the operator (2.13) applied to cur;
+    //   kick mode (1.1): new = lf_cb*cur + lf_ca*prev + lf_cf*acc, acc = -A L1 u - B L2 w
+    //     summed in full (the exact-part coefficients kappa0, beta0 are not
+    //     subtracted), from the term pairs of (u, w) = (cur, difference quotient)
     int lffp;
     double* s_prev;
     double* s_cur;
@@ -650,6 +653,9 @@ void k_c2r0(C2RArgs<T> a) {
 
     // delta at this thread's points, held in registers (FP64)
     const SolveScalars sc = a.sc[item * a.sc_stride];
+    // the leap-frog kick sums the full operators (no exact part to subtract)
+    const double kap0 = a.lffp ? 0.0 : sc.kappa0;
+    const double bet0 = a.lffp ? 0.0 : sc.beta0;
     double dl[E];
     if constexpr (MODE != C2R_EXPORT) {
         const double* dptr = a.delta + (long long)item * a.coef_stride + colc;
@@ -708,7 +714,7 @@ void k_c2r0(C2RArgs<T> a) {
             if (tr == 0) {
 #pragma unroll
                 for (int e = 0; e < E; ++e) {
-                    acc[e] = T(sc.kappa0 + double(cA[e])) * y[e].x + T(sc.beta0 + double(cB[e])) * y[e].y;
+                    acc[e] = T(kap0 + double(cA[e])) * y[e].x + T(bet0 + double(cB[e])) * y[e].y;
                     dm[e] = dl[e];
                 }
             } else {
@@ -721,8 +727,8 @@ void k_c2r0(C2RArgs<T> a) {
                 }
             }
         } else if constexpr (MODE == C2R_KICK) {
-            const double k0c = (tr == 0) ? sc.kappa0 : 0.0;
-            const double b0c = (tr == 0) ? sc.beta0 : 0.0;
+            const double k0c = (tr == 0) ? kap0 : 0.0;
+            const double b0c = (tr == 0) ? bet0 : 0.0;
 #pragma unroll
             for (int e = 0; e < E; ++e) {
                 const T ca = T(k0c + double(cA[e]) * dm[e]);
@@ -803,6 +809,23 @@ void k_c2r0(C2RArgs<T> a) {
             }
         }
         return;
+    }
+    if constexpr (MODE == C2R_KICK) {
+        if (a.lffp) {  // leap-frog update of (1.1) at this thread's points
+            if (active) {
+                const long long ib = (long long)item * a.Nreal + colc;
+                bool ok = true;
+#pragma unroll
+                for (int e = 0; e < E; ++e) {
+                    T f = acc[e];
+                    if constexpr (SPLIT) f += cA[e] * S1[e] + cB[e] * S2[e];
+                    const long long ix = ib + (long long)(t + TP * e) * a.inner;
+                    ok &= lffp_point(a.s_prev + ix, a.s_cur + ix, double(f), -1.0, 0.0, a.lf_cb, a.lf_ca, a.lf_cf);
+                }
+                if (!ok) a.flag[0] = 1;
+            }
+            return;  // uniform over the workgroup
+        }
     }
     // kick: right-hand side, finiteness flag, forward axis-0 transform, half rows out
     cpx<T> z[E];
@@ -959,8 +982,8 @@ __global__ __launch_bounds__(64 * NW_) void k_c2r0w(C2RArgs<T> a) {
                 dm[e] *= dl[e] * dl[e];
             }
         } else if constexpr (MODE == C2R_KICK) {
-            const double k0c = (tr == 0) ? sc.kappa0 : 0.0;
-            const double b0c = (tr == 0) ? sc.beta0 : 0.0;
+            const double k0c = (tr == 0 && !a.lffp) ? sc.kappa0 : 0.0;
+            const double b0c = (tr == 0 && !a.lffp) ? sc.beta0 : 0.0;
 #pragma unroll
             for (int e = 0; e < E; ++e) {
                 const T ca = T(k0c + double(cA[e]) * dm[e]);
@@ -1009,6 +1032,22 @@ __global__ __launch_bounds__(64 * NW_) void k_c2r0w(C2RArgs<T> a) {
         }
         if (!ok) a.flag[0] = 1;
         return;
+    }
+    if constexpr (MODE == C2R_KICK) {
+        if (a.lffp) {  // leap-frog update of (1.1) at this thread's points
+            if (active) {
+                const long long ib = (long long)item * a.Nreal + colc;
+                bool ok = true;
+#pragma unroll
+                for (int e = 0; e < E; ++e) {
+                    const long long ix = ib + (long long)(t + TP * e) * a.inner;
+                    ok &= lffp_point(a.s_prev + ix, a.s_cur + ix, double(acc[e]), -1.0, 0.0, a.lf_cb, a.lf_ca,
+                                     a.lf_cf);
+                }
+                if (!ok) a.flag[0] = 1;
+            }
+            return;  // uniform over the workgroup
+        }
     }
     // kick: right-hand side, finiteness flag, forward transform, half rows out
     cpx<T> z[E];
@@ -1062,6 +1101,7 @@ struct Args1D {
     double dt, invN;
     int* flag;
     double lf_cb, lf_ca, lf_cf;   // leap-frog first-step coefficients (k_1d_lffp)
+    double lf_wc, lf_wp;          // (1.1): first-step damping argument w = lf_wc cur + lf_wp prev
     // sub-steps per step (1: TSFP2; 3: the fourth-order composition with
     // sub-step weights w1, w0, w1)
     int sub;
@@ -1343,6 +1383,8 @@ __global__ __launch_bounds__(256) void k_convert(const TI* __restrict__ in, TO* 
 // for all nsteps steps; (u_in, v_in) = (cur, prev) in, (u_out, v_out) =
 // (cur, prev) out (may alias the inputs: every value is read before any is
 // written, by the thread that owns it). Generic model: kappa0 = kappa.
+// Seismic model (1.1): new = cb cur + ca prev + cf (-A L1 cur - B L2 w) with
+// w = (cur - prev)/dt (first step: lf_wc cur + lf_wp prev).
 // ---------------------------------------------------------------------------
 template <typename T, int N, int E>
 __global__ __launch_bounds__(N / E) void k_1d_lffp(Args1D<T> a) {
@@ -1398,10 +1440,68 @@ __global__ __launch_bounds__(N / E) void k_1d_lffp(Args1D<T> a) {
         }
         dl[e] = dd[j];
     }
+    const bool seismic = a.model == MODEL_SEISMIC;
+    double Ar[E], Br[E];
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+        const long long j = (long long)item * a.coef_stride + t + TP * e;
+        Ar[e] = double(a.A[j]);
+        Br[e] = double(a.B[j]);
+    }
     bool ok = true;
     for (int step = 0; step < a.nsteps; ++step) {
         const double cb = step == 0 ? a.lf_cb : 2.0, ca = step == 0 ? a.lf_ca : -1.0;
         const double cf = step == 0 ? a.lf_cf : a.dt * a.dt;
+        if (seismic) {
+            // L1 cur and L2 w: both forward transforms in FP64, then one
+            // complex inverse transform per term carrying the pair (t1_m, t2_m)
+            const double wc = step == 0 ? a.lf_wc : 1.0 / a.dt;
+            const double wp = step == 0 ? a.lf_wp : -1.0 / a.dt;
+            cpx<double> x1[E], x2[E];
+#pragma unroll
+            for (int e = 0; e < E; ++e) {
+                x1[e] = {cur[e], 0.0};
+                x2[e] = {wc * cur[e] + wp * prev[e], 0.0};
+            }
+            fft_pencil<double, N, E, -1>(x1, t, lds64, tw64_s);
+            fft_pencil<double, N, E, -1>(x2, t, lds64, tw64_s);
+            double acc1[E], acc2[E], dp[E];
+#pragma unroll
+            for (int e = 0; e < E; ++e) {
+                const double P1 = Pv(e);
+                const double P2 = P1 > 0.0 ? exp(sc.sig2 * Lv(e)) : 0.0;  // zero at k = 0 like P1
+                x1[e] = {P1 * x1[e].x * a.invN, P1 * x1[e].y * a.invN};
+                x2[e] = {P2 * x2[e].x * a.invN, P2 * x2[e].y * a.invN};
+                acc1[e] = 0.0;
+                acc2[e] = 0.0;
+                dp[e] = 1.0;
+            }
+            for (int m = 0; m <= a.M; ++m) {
+                cpx<T> y[E];
+#pragma unroll
+                for (int e = 0; e < E; ++e) y[e] = {T(x1[e].x - x2[e].y), T(x1[e].y + x2[e].x)};
+                fft_pencil<T, N, E, +1>(y, t, lds, tw_s);
+                const double inv = 1.0 / double(m + 1);
+#pragma unroll
+                for (int e = 0; e < E; ++e) {
+                    acc1[e] += dp[e] * double(y[e].x);
+                    acc2[e] += dp[e] * double(y[e].y);
+                    dp[e] *= dl[e];
+                    const double f = Lv(e) * inv;
+                    x1[e] = {x1[e].x * f, x1[e].y * f};
+                    x2[e] = {x2[e].x * f, x2[e].y * f};
+                }
+            }
+#pragma unroll
+            for (int e = 0; e < E; ++e) {
+                const double u = cur[e];
+                const double nw = cb * u + ca * prev[e] + cf * (-Ar[e] * acc1[e] - Br[e] * acc2[e]);
+                ok &= isfinite(nw);
+                prev[e] = u;
+                cur[e] = nw;
+            }
+            continue;
+        }
         cpx<double> x[E];
 #pragma unroll
         for (int e = 0; e < E; ++e) x[e] = {cur[e], 0.0};

@@ -73,6 +73,9 @@ struct Geometry {
 
 bool is_fp32(const vofl_desc* d) { return d->precision == VOFL_FP32; }
 
+// FP64 fields of the leap-frog state per solve (2D/3D plans)
+int lffp_fields(int model) { return model == VOFL_MODEL_SEISMIC ? 3 : 2; }
+
 bool supported_len(int ndim, int n, bool fp32) {
     if (ndim == 1) return fp32 ? Launch<float>::supported_1d(n) : Launch<double>::supported_1d(n);
     return fp32 ? Launch<float>::supported_multi(n) : Launch<double>::supported_multi(n);
@@ -113,8 +116,15 @@ int derive(const vofl_desc* d, Geometry& g) {
     g.ncoef = d->coef_per_solve ? g.batch : 1;
     const long long ncv = (long long)g.ncoef * g.Nreal;
     if (d->model == VOFL_MODEL_SEISMIC) {
-        if (!(std::isfinite(d->c0) && d->c0 > 0 && std::isfinite(d->omega0) && d->omega0 > 0))
-            return fail(VOFL_ERR_INVALID, "c0 and omega0 must be finite and > 0");
+        if (!(std::isfinite(d->omega0) && d->omega0 > 0)) return fail(VOFL_ERR_INVALID, "omega0 must be finite and > 0");
+        if (d->c0_field) {
+            for (long long i = 0; i < ncv; ++i) {
+                const double c = d->c0_field[i];
+                if (!(std::isfinite(c) && c > 0)) return fail(VOFL_ERR_INVALID, "c0_field[%lld] = %g must be > 0", i, c);
+            }
+        } else if (!(std::isfinite(d->c0) && d->c0 > 0)) {
+            return fail(VOFL_ERR_INVALID, "c0 must be finite and > 0");
+        }
         if ((d->Q == nullptr) == (d->gamma == nullptr))
             return fail(VOFL_ERR_INVALID, "give exactly one of Q and gamma");
         if (d->Q) {
@@ -164,8 +174,8 @@ int derive(const vofl_desc* d, Geometry& g) {
         bytes += (size_t)slots * g.H * celt;                  // work slots
         g.stage_fields = std::max(2 * g.batch, g.max_batch);
         bytes += (size_t)g.stage_fields * g.H * 16;           // FP64 state / forward staging
-        if (d->model == VOFL_MODEL_GENERIC)
-            bytes += (size_t)2 * g.batch * g.Nreal * 8;        // FP64 leap-frog state (u^{n-1}, u^n)
+        // FP64 leap-frog state (u^{n-1}, u^n; for (1.1) also the difference quotient w)
+        bytes += (size_t)lffp_fields(d->model) * g.batch * g.Nreal * 8;
     }
     if (d->model == VOFL_MODEL_GENERIC && g.batch == 1)
         bytes += (size_t)CN_VECTORS * g.Nreal * g.elt + CN_SCALARS * 8;  // Crank-Nicolson solver vectors
@@ -204,6 +214,7 @@ struct vofl_plan_s {
     cpx<double>* tw64[3] = {nullptr, nullptr, nullptr};
     double* delta = nullptr;
     double* LS = nullptr;              // leap-frog FP64 state: u^{n-1} of every solve, then u^n
+                                       // (seismic model: then w, the difference quotient)
     void* cnv = nullptr;               // Crank-Nicolson vectors (CN_VECTORS x N)
     double* cns = nullptr;             // Crank-Nicolson reduction scalars
     int sub = 1;                       // sub-steps per step (3: fourth-order composition)
@@ -382,8 +393,7 @@ int upload_tables(vofl_plan_s* p, const std::vector<double>& delta, const std::v
         // FP64 staging of forward transforms (apply fields use it from the start)
         if ((rc = dalloc(p, (cpx<double>**)&p->U, (size_t)g.stage_fields * g.H * sizeof(cpx<double>)))) return rc;
         p->V = (cpx<double>*)p->U + (size_t)g.batch * g.H;
-        if (p->model == VOFL_MODEL_GENERIC &&
-            (rc = dalloc(p, &p->LS, (size_t)2 * g.batch * g.Nreal * sizeof(double))))
+        if ((rc = dalloc(p, &p->LS, (size_t)lffp_fields(p->model) * g.batch * g.Nreal * sizeof(double))))
             return rc;
     }
     if (p->model == VOFL_MODEL_GENERIC && g.batch == 1) {
@@ -527,7 +537,13 @@ int apply_multi(vofl_plan_s* p, int op, const TIN* u, T* out, int nf, hipStream_
 // (cb0, ca0, cf0) in place of (2, -1, dt^2) (the start (3.4c) is such a step
 // with (1, dt, dt^2/2) on (prev, cur) = (psi, phi))
 template <typename T>
-int lffp_multi(vofl_plan_s* p, double cb0, double ca0, double cf0, int nsteps, hipStream_t s) {
+int lffp_seismic_multi(vofl_plan_s* p, double cb0, double ca0, double cf0, double wc0, double wp0, int nsteps,
+                       hipStream_t s);
+
+template <typename T>
+int lffp_multi(vofl_plan_s* p, double cb0, double ca0, double cf0, double wc0, double wp0, int nsteps,
+               hipStream_t s) {
+    if (p->model == VOFL_MODEL_SEISMIC) return lffp_seismic_multi<T>(p, cb0, ca0, cf0, wc0, wp0, nsteps, s);
     const Geometry& g = p->g;
     double* prev = p->LS;
     double* cur = p->LS + (size_t)g.batch * g.Nreal;
@@ -540,6 +556,72 @@ int lffp_multi(vofl_plan_s* p, double cb0, double ca0, double cf0, int nsteps, h
 }
 
 
+
+// Leap-frog steps for (1.1) on the plan's FP64 state (u^{n-1}, u^n, w):
+// per step w = wc u^n + wp u^{n-1} ((u^n - u^{n-1})/dt; the first step uses
+// (wc0, wp0)), forward transforms of (u^n, w) in FP64, the 2(M+1) term
+// spectra l_m |mu|^{2 sigma_1} u_hat and l_m |mu|^{2 sigma_2} w_hat along the
+// last (and middle) axis, and the axis-0 pass that sums -A L1 u - B L2 w by
+// (2.13) and updates the state in place.
+template <typename T>
+int lffp_seismic_multi(vofl_plan_s* p, double cb0, double ca0, double cf0, double wc0, double wp0, int nsteps,
+                       hipStream_t s) {
+    const Geometry& g = p->g;
+    const int items = g.batch;
+    const long long n = (long long)items * g.Nreal;
+    const long long SS = (long long)g.step_slots * g.H;
+    double* prev = p->LS;
+    double* cur = p->LS + n;
+    double* wq = p->LS + 2 * n;
+    cpx<T>* W = (cpx<T>*)p->work;
+    cpx<double>* U = (cpx<double>*)p->U;
+    cpx<double>* V = (cpx<double>*)p->V;
+    hipError_t e;
+    ContigArgs<T, double> a = contig_base<T, double>(p);
+    a.in = U;
+    a.in_istride = g.H;
+    a.in_fstride = (long long)items * g.H;
+    a.nin = 2;
+    a.tw_in = p->tw64[g.ndim - 1];
+    a.out = W;
+    a.out_istride = SS;
+    a.in_kind = IN_APPLY;     // no state in the spectral blocks
+    a.emit_kind = EMIT_STEP;  // slot pairs (t1_m, t2_m), m = 0..M
+    a.do_prop = 0;
+    C2RArgs<T> c = c2r_base<T>(p);
+    c.in = W;
+    c.istride = SS;
+    c.mode = C2R_KICK;
+    c.lffp = 1;
+    c.s_prev = prev;
+    c.s_cur = cur;
+    for (int k = 0; k < nsteps; ++k) {
+        const double wc = k == 0 ? wc0 : 1.0 / p->dt, wp = k == 0 ? wp0 : -1.0 / p->dt;
+        c.lf_cb = k == 0 ? cb0 : 2.0;
+        c.lf_ca = k == 0 ? ca0 : -1.0;
+        c.lf_cf = k == 0 ? cf0 : p->dt * p->dt;
+        const double* w = prev;  // the start passes w = psi in the prev slot
+        if (!(wc == 0.0 && wp == 1.0)) {
+            e = p->timed("lffp_w", s, [&] {
+                return Launch<double>::lincomb(wq, cur, wc, prev, wp, nullptr, 0.0, nullptr, 0.0, n, s);
+            });
+            if (e != hipSuccess) return hip_fail(e, "difference quotient launch");
+            w = wq;
+        }
+        if ((e = forward_to_stage<double>(p, cur, U, items, s)) != hipSuccess) return hip_fail(e, "r2c0 launch");
+        if ((e = forward_to_stage<double>(p, w, V, items, s)) != hipSuccess) return hip_fail(e, "r2c0 launch");
+        if ((e = mid<double>(p, "mid_lffp_fwd", -1, U, g.H, 1, 2 * items, p->tw64[1 % g.ndim], s)) != hipSuccess)
+            return hip_fail(e, "mid launch");
+        e = p->timed("contig_lffp", s, [&] { return Launch<T>::contig(g.nlast, a, items, s); });
+        if (e != hipSuccess) return hip_fail(e, "contig launch");
+        if ((e = mid<T>(p, "mid_lffp_terms", +1, W, SS, g.nterm, items, (const cpx<T>*)p->tw[1 % g.ndim], s)) !=
+            hipSuccess)
+            return hip_fail(e, "mid launch");
+        e = p->timed("c2r0_lffp", s, [&] { return Launch<T>::c2r0(g.n[0], c, items, s, p->c2r_variant); });
+        if (e != hipSuccess) return hip_fail(e, "c2r0 launch");
+    }
+    return VOFL_OK;
+}
 
 // length of sub-step k (dt for TSFP2; dt w1, dt w0, dt w1 for the composition)
 double substep_len_h(const vofl_plan_s* p, int k) {
@@ -657,7 +739,7 @@ Args1D<T> args_1d(vofl_plan_s* p) {
 // leap-frog on caller fields: (cur, prev) in, nsteps steps, (cur, prev) out
 template <typename T>
 int lffp_any(vofl_plan_s* p, const void* cur_in, const void* prev_in, void* cur_out, void* prev_out,
-             double cb0, double ca0, double cf0, int nsteps, hipStream_t s) {
+             double cb0, double ca0, double cf0, double wc0, double wp0, int nsteps, hipStream_t s) {
     const Geometry& g = p->g;
     if (g.ndim == 1) {
         Args1D<T> a = args_1d<T>(p);
@@ -669,6 +751,8 @@ int lffp_any(vofl_plan_s* p, const void* cur_in, const void* prev_in, void* cur_
         a.lf_cb = cb0;
         a.lf_ca = ca0;
         a.lf_cf = cf0;
+        a.lf_wc = wc0;
+        a.lf_wp = wp0;
         hipError_t e = p->timed("1d_lffp", s, [&] { return Launch<T>::d1_lffp(a.N, a, g.batch, s); });
         return e == hipSuccess ? VOFL_OK : hip_fail(e, "1d leap-frog launch");
     }
@@ -678,7 +762,7 @@ int lffp_any(vofl_plan_s* p, const void* cur_in, const void* prev_in, void* cur_
     hipError_t e = Launch<T>::to_f64((const T*)cur_in, cur, n, s);
     if (e == hipSuccess) e = Launch<T>::to_f64((const T*)prev_in, prev, n, s);
     if (e != hipSuccess) return hip_fail(e, "state load");
-    int rc = lffp_multi<T>(p, cb0, ca0, cf0, nsteps, s);
+    int rc = lffp_multi<T>(p, cb0, ca0, cf0, wc0, wp0, nsteps, s);
     if (rc) return rc;
     e = Launch<T>::from_f64(cur, (T*)cur_out, n, s);
     if (e == hipSuccess) e = Launch<T>::from_f64(prev, (T*)prev_out, n, s);
@@ -991,12 +1075,21 @@ int vofl_plan(const vofl_desc* d, void* stream, vofl_plan_t* out) {
             s.beta0 = 0.0;
             s.lambda = d->lambda;
         } else {
+            // per-point phase velocity (layered media) or the scalar c0; the
+            // exact part uses the grid mean of c0
+            const double* cf = d->c0_field ? d->c0_field + off : nullptr;
             parallel_for(N, [&](long long i) {
                 delta[off + i] = f[i] - mean;
-                seismic_AB(f[i], d->c0, d->omega0, A[off + i], B[off + i]);
+                seismic_AB(f[i], cf ? cf[i] : d->c0, d->omega0, A[off + i], B[off + i]);
             });
+            double cbar = d->c0;
+            if (cf) {
+                long double cs = 0.0L;
+                for (long long i = 0; i < N; ++i) cs += cf[i];
+                cbar = (double)(cs / (long double)N);
+            }
             double k0, b0;
-            seismic_AB(mean, d->c0, d->omega0, k0, b0);
+            seismic_AB(mean, cbar, d->omega0, k0, b0);
             s.sig1 = 1.0 + mean;
             s.sig2 = 0.5 + mean;
             s.kappa0 = k0;
@@ -1139,12 +1232,12 @@ int vofl_lffp_start(vofl_plan_t p, const void* phi, const void* psi, void* u_pre
     if (!p) return fail(VOFL_ERR_INVALID, "plan is NULL");
     if (!phi || !psi || !u_prev || !u) return fail(VOFL_ERR_INVALID, "phi, psi, u_prev and u must be device pointers");
     if (u_prev == u) return fail(VOFL_ERR_INVALID, "u_prev and u must be distinct");
-    if (p->model != VOFL_MODEL_GENERIC)
-        return fail(VOFL_ERR_UNSUPPORTED, "the leap-frog scheme is provided for the generic model (1.5)");
     hipStream_t s = (hipStream_t)stream;
     const double dt = p->dt;
-    return p->precision == VOFL_FP32 ? lffp_any<float>(p, phi, psi, u, u_prev, 1.0, dt, 0.5 * dt * dt, 1, s)
-                                     : lffp_any<double>(p, phi, psi, u, u_prev, 1.0, dt, 0.5 * dt * dt, 1, s);
+    // (prev, cur) = (psi, phi): u^1 = phi + dt psi + dt^2/2 F(phi, w = psi)
+    return p->precision == VOFL_FP32
+               ? lffp_any<float>(p, phi, psi, u, u_prev, 1.0, dt, 0.5 * dt * dt, 0.0, 1.0, 1, s)
+               : lffp_any<double>(p, phi, psi, u, u_prev, 1.0, dt, 0.5 * dt * dt, 0.0, 1.0, 1, s);
 }
 
 int vofl_lffp_step(vofl_plan_t p, void* u_prev, void* u, int nsteps, void* stream) {
@@ -1152,13 +1245,12 @@ int vofl_lffp_step(vofl_plan_t p, void* u_prev, void* u, int nsteps, void* strea
     if (!u_prev || !u) return fail(VOFL_ERR_INVALID, "u_prev and u must be device pointers");
     if (u_prev == u) return fail(VOFL_ERR_INVALID, "u_prev and u must be distinct");
     if (nsteps < 0) return fail(VOFL_ERR_INVALID, "nsteps must be >= 0");
-    if (p->model != VOFL_MODEL_GENERIC)
-        return fail(VOFL_ERR_UNSUPPORTED, "the leap-frog scheme is provided for the generic model (1.5)");
     if (nsteps == 0) return VOFL_OK;
     hipStream_t s = (hipStream_t)stream;
-    const double dt2 = p->dt * p->dt;
-    return p->precision == VOFL_FP32 ? lffp_any<float>(p, u, u_prev, u, u_prev, 2.0, -1.0, dt2, nsteps, s)
-                                     : lffp_any<double>(p, u, u_prev, u, u_prev, 2.0, -1.0, dt2, nsteps, s);
+    const double dt2 = p->dt * p->dt, idt = 1.0 / p->dt;
+    return p->precision == VOFL_FP32
+               ? lffp_any<float>(p, u, u_prev, u, u_prev, 2.0, -1.0, dt2, idt, -idt, nsteps, s)
+               : lffp_any<double>(p, u, u_prev, u, u_prev, 2.0, -1.0, dt2, idt, -idt, nsteps, s);
 }
 
 int vofl_cnfp_step(vofl_plan_t p, void* u_prev, void* u, int nsteps, double tol, int max_iter,

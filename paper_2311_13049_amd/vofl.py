@@ -62,6 +62,7 @@ class vofl_desc(ctypes.Structure):
         ("hbm_budget", ctypes.c_size_t),
         ("tune_steps", ctypes.c_int),
         ("order", ctypes.c_int),
+        ("c0_field", _c_double_p),
     ]
 
 
@@ -122,8 +123,9 @@ def _check(rc: int) -> int:
 
 def make_desc(shape, lo, hi, *, model="seismic", c0=1.0, omega0=1.0, Q=None, gamma=None,
               s=None, kappa=1.0, lam=0.0, M=8, dt=1e-3, precision="fp64", max_batch=1,
-              batch=1, coef_per_solve=False, hbm_budget=0, tune_steps=0, order=2):
-    """Build a vofl_desc; returns (desc, keepalive) where keepalive holds the host arrays."""
+              batch=1, coef_per_solve=False, hbm_budget=0, tune_steps=0, order=2, c0_field=None):
+    """Build a vofl_desc; returns (desc, keepalive) where keepalive holds the host arrays.
+    c0_field: per-point phase velocities (layered media; replaces c0)."""
     shape = tuple(int(n) for n in shape)
     d = vofl_desc()
     d.ndim = len(shape)
@@ -155,6 +157,7 @@ def make_desc(shape, lo, hi, *, model="seismic", c0=1.0, omega0=1.0, Q=None, gam
     d.hbm_budget = int(hbm_budget)
     d.tune_steps = int(tune_steps)
     d.order = int(order)
+    d.c0_field = arr(c0_field)
     return d, keep
 
 

@@ -16,6 +16,12 @@ Recipes (all seeds are explicit):
              periodic wrap), times (1 + 0.05 U(-1,1)) per point.
 * ``gaussian_pulse``  exp(-|x - xs|^2) with periodic minimum-image distance.
 * paper test functions of Section 4.1: s1, s2 and the initial data of (4.1).
+* ``ex3``    Example 3 of Section 4 (two-layer attenuating medium) on the
+             periodic box [0,2)^2: gamma = a1 + a2 tanh(100 (y - 1)), phase
+             velocity 11/18 for y > 1 and 1 for y <= 1, Ricker initial
+             displacement (4.3) with nu0 = 25 centred at (1, 0.85), zero
+             initial velocity, dt = 1e-4. The paper's mesh h = 0.002 gives
+             n = 1000 per axis; omega0 = 1 and M = 8 are not given there.
 """
 
 from __future__ import annotations
@@ -26,6 +32,7 @@ __all__ = [
     "BASE_SEED", "rng_for", "grid_1d", "mesh", "gaussian_pulse", "grf_Q",
     "two_layer_Q", "c1_inputs", "c2_inputs", "c3_inputs", "c4_inputs",
     "c5_requests", "c5_request_inputs", "paper_s1", "paper_s2", "paper_ex1_initial",
+    "ricker", "ex3_inputs",
 ]
 
 BASE_SEED = 13049
@@ -190,3 +197,26 @@ def paper_s2(x):
 def paper_ex1_initial(x):
     """Initial data of problem (4.1): u(x,0) = exp(-x^2), u_t(x,0) = 0."""
     return np.exp(-x * x), np.zeros_like(x)
+
+
+def ricker(shape, lo, hi, center, nu0: float) -> np.ndarray:
+    """(1 - 2 pi^2 nu0^2 r^2) exp(-pi^2 nu0^2 r^2), r = |x - xc| (initial data (4.3))."""
+    X = mesh(shape, lo, hi)
+    r2 = np.zeros(tuple(shape))
+    for Xi, c in zip(X, center):
+        r2 = r2 + (Xi - c) ** 2
+    a = (np.pi * nu0) ** 2 * r2
+    return (1.0 - 2.0 * a) * np.exp(-a)
+
+
+def ex3_inputs(n: int = 1000, case: int = 0):
+    """Example 3 (Section 4): case 0 has (a1, a2) = (0.0065, 0.0035), case 1
+    (0.02, 0.01); y is the last axis."""
+    a1, a2 = ((0.0065, 0.0035), (0.02, 0.01))[case]
+    shape, lo, hi = (n, n), (0.0, 0.0), (2.0, 2.0)
+    _, Y = mesh(shape, lo, hi)
+    gamma = a1 + a2 * np.tanh(100.0 * (Y - 1.0))
+    c0 = np.where(Y > 1.0, 11.0 / 18.0, 1.0)
+    phi = ricker(shape, lo, hi, (1.0, 0.85), 25.0)
+    return dict(shape=shape, lo=lo, hi=hi, gamma=gamma, c0=c0, omega0=1.0, M=8, dt=1e-4,
+                phi=phi, psi=np.zeros(shape), a1=a1, a2=a2)
