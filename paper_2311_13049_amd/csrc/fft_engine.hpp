@@ -85,6 +85,27 @@ __device__ __forceinline__ void dft3(cpx<T>* v) {
     v[2] = csub(m, r);
 }
 
+// 5-point DFT: with a1 = v1+v4, b1 = v1-v4, a2 = v2+v3, b2 = v2-v3 and
+// theta = 2 pi/5, X1,4 = v0 + a1 cos(theta) + a2 cos(2 theta) -/+ i s (b1 sin(theta) + b2 sin(2 theta))
+// and X2,3 = v0 + a1 cos(2 theta) + a2 cos(theta) -/+ i s (b1 sin(2 theta) - b2 sin(theta)),
+// s = -DIR (the sign of the exponent)
+template <int DIR, typename T>
+__device__ __forceinline__ void dft5(cpx<T>* v) {
+    const T c1 = T(0.30901699437494742410), c2 = T(-0.80901699437494742410);  // cos(2 pi/5), cos(4 pi/5)
+    const T s1 = T(0.95105651629515357212), s2 = T(0.58778525229247312917);   // sin(2 pi/5), sin(4 pi/5)
+    const cpx<T> a1 = cadd(v[1], v[4]), b1 = csub(v[1], v[4]);
+    const cpx<T> a2 = cadd(v[2], v[3]), b2 = csub(v[2], v[3]);
+    const cpx<T> m1 = {v[0].x + c1 * a1.x + c2 * a2.x, v[0].y + c1 * a1.y + c2 * a2.y};
+    const cpx<T> m2 = {v[0].x + c2 * a1.x + c1 * a2.x, v[0].y + c2 * a1.y + c1 * a2.y};
+    const cpx<T> t1 = mul_i<DIR>(cpx<T>{s1 * b1.x + s2 * b2.x, s1 * b1.y + s2 * b2.y});
+    const cpx<T> t2 = mul_i<DIR>(cpx<T>{s2 * b1.x - s1 * b2.x, s2 * b1.y - s1 * b2.y});
+    v[0] = cadd(v[0], cadd(a1, a2));
+    v[1] = cadd(m1, t1);
+    v[4] = csub(m1, t1);
+    v[2] = cadd(m2, t2);
+    v[3] = csub(m2, t2);
+}
+
 template <int DIR, typename T>
 __device__ __forceinline__ void dft4(cpx<T>* v) {
     cpx<T> a0 = cadd(v[0], v[2]);
@@ -168,16 +189,18 @@ __device__ __forceinline__ void dft(cpx<T>* v) {
     if constexpr (R == 2) dft2<DIR>(v);
     else if constexpr (R == 3) dft3<DIR>(v);
     else if constexpr (R == 4) dft4<DIR>(v);
+    else if constexpr (R == 5) dft5<DIR>(v);
     else if constexpr (R == 8) dft8<DIR>(v);
     else if constexpr (R == 16) dft16<DIR>(v);
     else static_assert(R == 1, "unsupported radix");
 }
 
-// radix of the next stage: the largest of 16, 8, 4, 3, 2 dividing both the
+// radix of the next stage: the first of 16, 8, 5, 4, 3, 2 dividing both the
 // remaining length and E
 constexpr int pick_radix(int rem, int E) {
     return (rem % 16 == 0 && E % 16 == 0) ? 16
          : (rem % 8 == 0 && E % 8 == 0)   ? 8
+         : (rem % 5 == 0 && E % 5 == 0)   ? 5
          : (rem % 4 == 0 && E % 4 == 0)   ? 4
          : (rem % 3 == 0 && E % 3 == 0)   ? 3
          : (rem % 2 == 0 && E % 2 == 0)   ? 2

@@ -99,15 +99,17 @@ constexpr int tile_width() {
     return (16 * col <= 67584) ? 16 : (8 * col <= 67584) ? 8 : 4;
 }
 // Tile width of k_c2r0: 16 columns unless the FFT buffer (N x W complex)
-// would exceed about 66 KB of LDS, and at most 512 threads at 8 elements
-// per thread.
+// would exceed about 66 KB of LDS, and at most 512 threads (a power of two).
 template <typename T, int N>
 constexpr int c2r_width() {
     constexpr int col = N * int(sizeof(cpx<T>));
     constexpr int w = (16 * col <= 67584) ? 16 : (8 * col <= 67584) ? 8 : 4;
-    constexpr int e = (N % 3 == 0) ? 12 : (N < 8 ? N : 8);  // elements per thread of k_c2r0
-    constexpr int lim = (512 / (N / e)) < 1 ? 1 : (512 / (N / e));
-    return w < lim ? w : lim;
+    // elements per thread of k_c2r0 (e_c2r0)
+    constexpr int e = (N % 5 == 0) ? 10 : (N % 3 == 0) ? 12 : (N < 8 ? N : 8);
+    int lim = (512 / (N / e)) < 1 ? 1 : (512 / (N / e));
+    int p2 = 1;
+    while (2 * p2 <= lim) p2 *= 2;
+    return w < p2 ? w : p2;
 }
 
 // Copy a length-N twiddle table into LDS (called by every thread before

@@ -10,14 +10,18 @@ namespace vofl {
 
 // Elements per thread of each kernel class for a transform length N. Lengths
 // with a factor 3 (3 * 2^k) use 12 elements per thread (radix 4 stages and
-// one radix-3 stage).
+// one radix-3 stage); lengths with a factor 5 (1000 = 2^3 5^3) use 10
+// (radix-5 and radix-2 stages, 100 threads per pencil).
 constexpr bool has3(int N) { return N % 3 == 0; }
-constexpr int e_contig(int N) { return has3(N) ? 12 : (N < 8 ? N : 8); }
-constexpr int e_mid(int N) { return has3(N) ? 12 : (N < 16 ? N : 16); }
-constexpr int e_r2c0(int N) { return has3(N) ? 12 : (N < 16 ? N : 16); }
-constexpr int e_c2r0(int N) { return has3(N) ? 12 : (N < 8 ? N : 8); }
+constexpr bool has5(int N) { return N % 5 == 0; }
+constexpr int e_contig(int N) { return has5(N) ? 10 : has3(N) ? 12 : (N < 8 ? N : 8); }
+constexpr int e_mid(int N) { return has5(N) ? 10 : has3(N) ? 12 : (N < 16 ? N : 16); }
+constexpr int e_r2c0(int N) { return has5(N) ? 10 : has3(N) ? 12 : (N < 16 ? N : 16); }
+constexpr int e_c2r0(int N) { return has5(N) ? 10 : has3(N) ? 12 : (N < 8 ? N : 8); }
 // 1D: one workgroup of at most 512 threads per field
-constexpr int e_1d(int N) { return has3(N) ? (N <= 1536 ? 6 : 12) : (N < 4 ? N : (N <= 2048 ? 4 : 8)); }
+constexpr int e_1d(int N) {
+    return has5(N) ? 10 : has3(N) ? (N <= 1536 ? 6 : 12) : (N < 4 ? N : (N <= 2048 ? 4 : 8));
+}
 // pencils per workgroup of k_contig: about 256 threads
 constexpr int p_contig(int N) { return (256 / (N / e_contig(N))) > 0 ? (256 / (N / e_contig(N))) : 1; }
 

@@ -5,8 +5,9 @@
 
 namespace vofl {
 
-#define VOFL_MULTI_SIZES(X) X(8) X(16) X(32) X(48) X(64) X(96) X(128) X(256) X(512) X(768) X(1024)
-#define VOFL_1D_SIZES(X) X(8) X(16) X(32) X(48) X(64) X(96) X(128) X(256) X(512) X(768) X(1024) X(2048) X(4096)
+#define VOFL_MULTI_SIZES(X) X(8) X(16) X(32) X(48) X(64) X(96) X(128) X(256) X(512) X(768) X(1000) X(1024)
+#define VOFL_1D_SIZES(X) \
+    X(8) X(16) X(32) X(48) X(64) X(96) X(128) X(256) X(512) X(768) X(1000) X(1024) X(2048) X(4096)
 
 template <typename T>
 bool Launch<T>::supported_multi(int N) {

@@ -47,6 +47,9 @@ CASES_ND = [
     ((32, 32, 32), (-4.0,) * 3, (4.0,) * 3),       # 3D cube
     ((48, 96), (-3.0, -6.0), (3.0, 6.0)),          # radix-3 lengths (48 = 3*16, 96 = 3*32)
     ((96, 16, 48), (-6.0, -1.0, -3.0), (6.0, 1.0, 3.0)),  # radix 3 on axes 0 and 2
+    ((1000, 16), (-62.5, -1.0), (62.5, 1.0)),      # radix 5 on axis 0 (1000 = 2^3 5^3), h = 1/8
+    ((16, 1000), (-1.0, -62.5), (1.0, 62.5)),      # radix 5 on the last axis
+    ((8, 1000, 8), (-0.5, -62.5, -0.5), (0.5, 62.5, 0.5)),  # radix 5 on the middle axis
 ]
 
 
@@ -115,8 +118,8 @@ def test_apply_constant_order_single_mode_exact():
 # step (3.13) for (1.1)
 # --------------------------------------------------------------------------
 
-@pytest.mark.parametrize("n", [96, 768])
-def test_apply_and_step_1d_radix3(n):
+@pytest.mark.parametrize("n", [96, 768, 1000])
+def test_apply_and_step_1d_mixed_radix(n):
     # h = 1/8 as in the 1D workload: the operator's amplification of FFT
     # rounding (|mu_max|^{2s}) stays where FP64 parity of 1e-12 is meaningful
     L = n / 16.0
@@ -156,6 +159,9 @@ STEP_CASES = [
     ((16, 8), (-2.0, -1.0), (2.0, 1.0), 4, 5),
     ((16, 16, 32), (-2.0, -2.0, -4.0), (2.0, 2.0, 4.0), 6, 6),
     ((8, 32, 8), (-1.0, -4.0, -1.0), (1.0, 4.0, 1.0), 3, 4),
+    ((1000, 32), (-62.5, -2.0), (62.5, 2.0), 6, 5),   # radix 5 on axis 0
+    ((32, 1000), (-2.0, -62.5), (2.0, 62.5), 6, 5),   # radix 5 on the last axis
+    ((8, 1000, 16), (-0.5, -62.5, -1.0), (0.5, 62.5, 1.0), 4, 3),  # radix 5 on the middle axis
 ]
 
 
