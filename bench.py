@@ -79,7 +79,7 @@ def main():
     ap.add_argument("--M", type=int, default=16)
     ap.add_argument("--precision", default="fp32")
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--workload", default="c3", choices=("c3", "c4", "c5", "lffp"))
+    ap.add_argument("--workload", default="c3", choices=("c3", "c4", "c5", "lffp", "ex3"))
     ap.add_argument("--requests", type=int, default=40, help="c5: requests in the trace")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain device copy of 1 GiB five times (HBM counter calibration)")
@@ -113,6 +113,8 @@ def main():
         return bench_c5(args, torch, V, dev)
     if args.workload == "lffp":
         return bench_lffp(args, torch, V, dev)
+    if args.workload == "ex3":
+        return bench_ex3(args, torch, V, dev)
     n, M = args.n, args.M
     c = c3_inputs(n=n)
     prec = args.precision
@@ -357,6 +359,90 @@ def bench_lffp(args, torch, V, dev):
         "roofline_c2r0_lffp": {"bound": "hbm", "achieved": alg_c2r / (c2r_ms / c2r_n / 1e3) / 1e9 if c2r_ms else None,
                                "peak": HBM_PEAK_GBS, "unit": "GB/s", "alg_bytes_per_launch": alg_c2r},
         "status": plan.sync_status(),
+    }
+    print(json.dumps(out), flush=True)
+
+
+def bench_ex3(args, torch, V, dev):
+    """Example 3 (Section 4): leap-frog for (1.1) in the two-layer attenuating
+    medium at the paper's mesh (1000 x 1000 on [0,2)^2, dt = 1e-4), M = 8."""
+    from workloads import ex3_inputs
+    ex = ex3_inputs(1000, case=0)
+    n, M, prec = ex["shape"][0], ex["M"], args.precision
+    N = n * n
+    tdt = torch.float32 if prec == "fp32" else torch.float64
+    plan = V.Plan(ex["shape"], ex["lo"], ex["hi"], gamma=ex["gamma"], c0_field=ex["c0"], omega0=ex["omega0"],
+                  M=M, dt=ex["dt"], precision=prec)
+    up, u = plan.lffp_start(torch.from_numpy(ex["phi"]).to(dev, tdt), torch.from_numpy(ex["psi"]).to(dev, tdt))
+    plan.lffp_step(up, u, args.warmup)
+    torch.cuda.synchronize()
+    plan.set_timing(True)
+    plan.lffp_step(up, u, 3)  # per-kernel times from events around each launch
+    torch.cuda.synchronize()
+    kt = plan.kernel_times()
+    plan.set_timing(False)
+    t0 = time.perf_counter()
+    plan.lffp_step(up, u, args.steps)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    status = plan.sync_status()
+    step_s = (t1 - t0) / args.steps
+    # both media of Example 3 as one batch of two solves (own gamma, same c0)
+    ex1 = ex3_inputs(1000, case=1)
+    del plan, up, u
+    pb = V.Plan(ex["shape"], ex["lo"], ex["hi"], gamma=np.stack([ex["gamma"], ex1["gamma"]]),
+                c0_field=np.stack([ex["c0"], ex1["c0"]]), omega0=ex["omega0"], M=M, dt=ex["dt"], precision=prec,
+                batch=2, coef_per_solve=True)
+    phi2 = torch.from_numpy(np.stack([ex["phi"], ex1["phi"]])).to(dev, tdt)
+    ub_prev, ub = pb.lffp_start(phi2, torch.zeros_like(phi2))
+    pb.lffp_step(ub_prev, ub, args.warmup)
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    pb.lffp_step(ub_prev, ub, args.steps)
+    torch.cuda.synchronize()
+    batch_step_s = (time.perf_counter() - t2) / args.steps
+    batch_status = pb.sync_status()
+    del pb, ub_prev, ub, phi2
+    elt = 4 if prec == "fp32" else 8
+    H = (n // 2 + 1) * n
+    # algorithmic bytes per step (read + write once): difference quotient
+    # (2 FP64 fields in, 1 out), two FP64 forward axis-0 passes, the last-axis
+    # pass (2 FP64 half spectra in, 2(M+1) term slots out) and the axis-0
+    # update pass (2(M+1) slots, delta, A, B, FP64 state in and out)
+    alg = {"lffp_w": 24 * N, "r2c0": 2 * (8 * N + 16 * H), "contig_lffp": 2 * 16 * H + 2 * (M + 1) * H * 2 * elt,
+           "c2r0_lffp": 2 * (M + 1) * H * 2 * elt + 8 * N + 2 * elt * N + 32 * N}
+    per_step = {k: ms / 3 for k, (ms, _) in kt.items()}
+    c2r_ms = kt["c2r0_lffp"][0] / kt["c2r0_lffp"][1] if "c2r0_lffp" in kt else None  # per launch
+    cpu = None
+    if not args.no_cpu:
+        import oracle as O
+        O.set_fft_workers(0)
+        t2 = time.perf_counter()
+        O.lffp_seismic(ex["phi"], ex["psi"], ex["gamma"], ex["c0"], ex["omega0"], ex["lo"], ex["hi"], M,
+                       ex["dt"], 2)
+        cpu_s = (time.perf_counter() - t2) / 2
+        cpu = {"value": 1.0 / cpu_s, "unit": "steps/s", "cores": 1, "kind": "oracle",
+               "sample": "start + 1 leap-frog step of the same 1000^2 Example 3 problem, FP64 numpy, one thread"}
+    out = {
+        "metric": "leap-frog steps/s, Example 3 two-layer medium (1.1), 1000^2, M=8",
+        "value": 1.0 / step_s, "unit": "steps/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": step_s * 1e3, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32" if prec == "fp32" else "f64", "data": "synthetic",
+        "config": {"workload": "Example 3 on [0,2)^2, 1000 x 1000 (h = 0.002), gamma = 0.0065 + 0.0035 tanh(100(y-1)), "
+                               "c0 = 11/18 (y > 1) / 1, omega0 = 1, Ricker start nu0 = 25 at (1, 0.85), "
+                               "dt = 1e-4, M = 8", "grid": [n, n], "M": M, "precision": prec},
+        "applies_per_s": 2.0 / step_s,
+        "kernel_ms_per_step": per_step,
+        "alg_bytes_per_step": alg,
+        "roofline": {"bound": "hbm", "kernel": "c2r0_lffp",
+                     "achieved": alg["c2r0_lffp"] / (c2r_ms / 1e3) / 1e9 if c2r_ms else None,
+                     "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": alg["c2r0_lffp"] / (c2r_ms / 1e3) / 1e9 / HBM_PEAK_GBS if c2r_ms else None,
+                     "traffic": None, "alg_bytes_per_launch": alg["c2r0_lffp"]},
+        "status": status,
+        "batch2_both_media": {"solve_steps_per_s": 2.0 / batch_step_s, "ms_per_batch_step": batch_step_s * 1e3,
+                              "status": batch_status},
+        "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)
 
