@@ -160,16 +160,18 @@ int vofl_lffp_start(vofl_plan_t plan, const void* phi, const void* psi, void* u_
 int vofl_lffp_step(vofl_plan_t plan, void* u_prev, void* u, int nsteps, void* stream);
 
 /* Crank-Nicolson Fourier pseudospectral scheme CNFP (eq. (3.2)) for the
- * generic model (1.5), plans with batch = 1: per step u^{n+1} = w solves
+ * generic model (1.5): per step u^{n+1} = w solves
  *   w + a L w - b lambda w^3 = 2 u^n - u^{n-1} - a L u^{n-1} + b lambda (u^{n-1})^3,
  * a = kappa dt^2/2, b = dt^2/2, L = (2.13). The nonlinear term is handled by
  * fixed-point iteration and every linear solve with I + a L by BiCGSTAB
  * (the operator is not symmetric), each to the relative tolerance tol in
  * (0, 1), at most max_iter (>= 1) iterations per solve. The start (3.3) is
  * the leap-frog start: use vofl_lffp_start. u_prev, u: as vofl_lffp_step.
- * *iterations (host, may be NULL) receives the total BiCGSTAB iterations.
- * The call synchronises stream (the iteration reads its scalars back).
- * Errors: VOFL_ERR_UNSUPPORTED (seismic model or batch > 1),
+ * The solves of a batched plan are advanced one after another, each with
+ * its own coefficients (the solver's vectors hold one solve).
+ * *iterations (host, may be NULL) receives the total BiCGSTAB iterations
+ * over all solves. The call synchronises stream (the iteration reads its
+ * scalars back). Errors: VOFL_ERR_UNSUPPORTED (seismic model),
  * VOFL_ERR_UNSTABLE (a solve did not reach tol). */
 int vofl_cnfp_step(vofl_plan_t plan, void* u_prev, void* u, int nsteps, double tol, int max_iter,
                    long long* iterations, void* stream);

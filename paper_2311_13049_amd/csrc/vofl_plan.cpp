@@ -177,7 +177,7 @@ int derive(const vofl_desc* d, Geometry& g) {
         // FP64 leap-frog state (u^{n-1}, u^n; for (1.1) also the difference quotient w)
         bytes += (size_t)lffp_fields(d->model) * g.batch * g.Nreal * 8;
     }
-    if (d->model == VOFL_MODEL_GENERIC && g.batch == 1)
+    if (d->model == VOFL_MODEL_GENERIC)
         bytes += (size_t)CN_VECTORS * g.Nreal * g.elt + CN_SCALARS * 8;  // Crank-Nicolson solver vectors
     g.bytes = bytes;
     if (d->hbm_budget && bytes > d->hbm_budget)
@@ -215,7 +215,9 @@ struct vofl_plan_s {
     double* delta = nullptr;
     double* LS = nullptr;              // leap-frog FP64 state: u^{n-1} of every solve, then u^n
                                        // (seismic model: then w, the difference quotient)
-    void* cnv = nullptr;               // Crank-Nicolson vectors (CN_VECTORS x N)
+    void* cnv = nullptr;               // Crank-Nicolson vectors (CN_VECTORS x N, one solve at a time)
+    int coef_item = 0;                 // solve whose coefficients single-field launches use
+                                       // (set by the Crank-Nicolson driver; else 0)
     double* cns = nullptr;             // Crank-Nicolson reduction scalars
     int sub = 1;                       // sub-steps per step (3: fourth-order composition)
     double w1 = 1.0, w0 = 1.0;         // composition weights
@@ -396,7 +398,7 @@ int upload_tables(vofl_plan_s* p, const std::vector<double>& delta, const std::v
         if ((rc = dalloc(p, &p->LS, (size_t)lffp_fields(p->model) * g.batch * g.Nreal * sizeof(double))))
             return rc;
     }
-    if (p->model == VOFL_MODEL_GENERIC && g.batch == 1) {
+    if (p->model == VOFL_MODEL_GENERIC) {
         if ((rc = dalloc(p, (T**)&p->cnv, (size_t)CN_VECTORS * g.Nreal * sizeof(T)))) return rc;
         if ((rc = dalloc(p, &p->cns, (size_t)CN_SCALARS * sizeof(double)))) return rc;
     }
@@ -406,6 +408,11 @@ int upload_tables(vofl_plan_s* p, const std::vector<double>& delta, const std::v
 // ---------------------------------------------------------------------------
 // launch sequences
 // ---------------------------------------------------------------------------
+
+// coefficient offsets of the solve p->coef_item (plans with one coefficient
+// field per solve; 0 otherwise)
+long long coef_off(const vofl_plan_s* p) { return p->g.ncoef > 1 ? (long long)p->coef_item * p->g.Nreal : 0; }
+int sc_off(const vofl_plan_s* p) { return p->g.ncoef > 1 ? p->coef_item : 0; }
 
 template <typename T, typename TI>
 ContigArgs<T, TI> contig_base(vofl_plan_s* p) {
@@ -418,7 +425,7 @@ ContigArgs<T, TI> contig_base(vofl_plan_s* p) {
     a.mu2_1 = (g.ndim == 3) ? p->mu2[1] : nullptr;
     a.mu2_l = p->mu2[g.ndim - 1];
     a.tw = (const cpx<T>*)p->tw[g.ndim - 1];
-    a.sc = p->sc;
+    a.sc = p->sc + sc_off(p);
     a.sc_stride = g.ncoef > 1 ? 1 : 0;
     a.U = (cpx<double>*)p->U;
     a.V = (cpx<double>*)p->V;
@@ -471,11 +478,11 @@ C2RArgs<T> c2r_base(vofl_plan_s* p) {
     c.tw = (const cpx<T>*)p->tw[0];
     c.M = p->M;
     c.model = p->model;
-    c.delta = p->delta;
-    c.A = (const T*)p->A;
-    c.B = (const T*)p->B;
+    c.delta = p->delta + coef_off(p);
+    c.A = (const T*)p->A + coef_off(p);
+    c.B = (const T*)p->B + coef_off(p);
     c.coef_stride = g.ncoef > 1 ? g.Nreal : 0;
-    c.sc = p->sc;
+    c.sc = p->sc + sc_off(p);
     c.sc_stride = g.ncoef > 1 ? 1 : 0;
     c.Nreal = g.Nreal;
     c.flag = p->flag;
@@ -719,11 +726,11 @@ Args1D<T> args_1d(vofl_plan_s* p) {
     a.mu2 = p->mu2[0];
     a.tw = (const cpx<T>*)p->tw[0];
     a.tw64 = p->tw64[0];
-    a.delta = p->delta;
-    a.A = (const T*)p->A;
-    a.B = (const T*)p->B;
+    a.delta = p->delta + coef_off(p);
+    a.A = (const T*)p->A + coef_off(p);
+    a.B = (const T*)p->B + coef_off(p);
     a.coef_stride = g.ncoef > 1 ? g.Nreal : 0;
-    a.sc = p->sc;
+    a.sc = p->sc + sc_off(p);
     a.sc_stride = g.ncoef > 1 ? 1 : 0;
     a.M = p->M;
     a.model = p->model;
@@ -789,15 +796,39 @@ int apply_any(vofl_plan_s* p, int op, const void* u, void* out, int nf, hipStrea
 // solve with I + a L by BiCGSTAB (the operator (2.13) is not symmetric).
 // Host-driven: the scalars of every iteration are read back.
 template <typename T>
+int cnfp_solve(vofl_plan_s* p, T* up, T* u, int nsteps, double tol, int max_iter, long long* iters,
+               hipStream_t s);
+
+// Crank-Nicolson steps of every solve of the plan, one solve after another
+// (each solve's applies use its own coefficients; the solver vectors are
+// reused)
+template <typename T>
 int cnfp_run(vofl_plan_s* p, T* up, T* u, int nsteps, double tol, int max_iter, long long* iters,
              hipStream_t s) {
+    const long long n = p->g.Nreal;
+    long long total = 0;
+    int rc = VOFL_OK;
+    for (int b = 0; b < p->g.batch && rc == VOFL_OK; ++b) {
+        p->coef_item = b;
+        long long it = 0;
+        rc = cnfp_solve<T>(p, up + b * n, u + b * n, nsteps, tol, max_iter, &it, s);
+        total += it;
+    }
+    p->coef_item = 0;
+    if (iters) *iters = total;
+    return rc;
+}
+
+template <typename T>
+int cnfp_solve(vofl_plan_s* p, T* up, T* u, int nsteps, double tol, int max_iter, long long* iters,
+               hipStream_t s) {
     const long long n = p->g.Nreal;
     T* V = (T*)p->cnv;
     T *r = V, *w = V + n, *x = V + 2 * n, *b = V + 3 * n, *res = V + 4 * n, *rh = V + 5 * n, *pv = V + 6 * n,
       *vv = V + 7 * n, *sv = V + 8 * n, *tv = V + 9 * n, *lw = V + 10 * n;
     double* part = p->cns;
     double* dres = p->cns + 2 * Launch<T>::dot_blocks;
-    const SolveScalars sc = p->sc_host[0];
+    const SolveScalars sc = p->sc_host[sc_off(p)];
     const double kap = sc.kappa0, lam = sc.lambda;
     const double a = 0.5 * kap * p->dt * p->dt, bb = 0.5 * p->dt * p->dt;
     hipError_t e = hipSuccess;
@@ -1261,8 +1292,8 @@ int vofl_cnfp_step(vofl_plan_t p, void* u_prev, void* u, int nsteps, double tol,
     if (nsteps < 0) return fail(VOFL_ERR_INVALID, "nsteps must be >= 0");
     if (!(tol > 0.0 && tol < 1.0)) return fail(VOFL_ERR_INVALID, "tol must be in (0, 1)");
     if (max_iter < 1) return fail(VOFL_ERR_INVALID, "max_iter must be >= 1");
-    if (p->model != VOFL_MODEL_GENERIC || p->g.batch != 1)
-        return fail(VOFL_ERR_UNSUPPORTED, "the Crank-Nicolson scheme is provided for the generic model (1.5) with batch 1");
+    if (p->model != VOFL_MODEL_GENERIC)
+        return fail(VOFL_ERR_UNSUPPORTED, "the Crank-Nicolson scheme is provided for the generic model (1.5)");
     if (iterations) *iterations = 0;
     if (nsteps == 0) return VOFL_OK;
     hipStream_t s = (hipStream_t)stream;

@@ -94,7 +94,7 @@ def test_valid_descriptors_and_footprint_formula():
     b = V.vofl_plan_footprint(d)
     slots = max((M + 2) + 3, 3 * (M + 1))
     expect = (n0 + n1) * (8 + 16 + 8) + 512 * (8 + 8) + 64 + 256 + slots * H * 8 + max(2, 3) * H * 16 + 2 * 512 * 8
-    expect += 11 * 512 * 4 + (2 * 512 + 8) * 8   # Crank-Nicolson vectors (batch 1) and scalars
+    expect += 11 * 512 * 4 + (2 * 512 + 8) * 8   # Crank-Nicolson vectors (one solve) and scalars
     assert b == expect
 
 

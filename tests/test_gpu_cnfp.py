@@ -86,7 +86,7 @@ def test_nd_vs_oracle(shape, precision):
     assert eu <= tol(precision) and ep <= tol(precision)
 
 
-def test_unsupported_plans_are_rejected():
+def test_seismic_plans_are_rejected():
     require_gpu()
     from paper_2311_13049_amd import vofl as V
     shape, lo, hi = (16, 16), (-2.0, -2.0), (2.0, 2.0)
@@ -96,10 +96,35 @@ def test_unsupported_plans_are_rejected():
     with pytest.raises(V.VoflError) as ei:
         p.cnfp_step(x, y, 1)
     assert ei.value.code == V.VOFL_ERR_UNSUPPORTED
-    q = _plan(shape, lo, hi, "fp64", s=np.full((2,) + shape, 1.1), kappa=1.0, lam=0.0, M=3, dt=1e-3, batch=2,
-              coef_per_solve=True)
-    xb = dev(np.zeros((2,) + shape), "fp64")
-    yb = dev(np.zeros((2,) + shape), "fp64")
-    with pytest.raises(V.VoflError) as ei:
-        q.cnfp_step(xb, yb, 1)
-    assert ei.value.code == V.VOFL_ERR_UNSUPPORTED
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+@pytest.mark.parametrize("shape,per_solve", [((256,), True), ((32, 48), True), ((32, 48), False)])
+def test_batched_solves_vs_oracle(shape, per_solve, precision):
+    """Three solves in one plan, each with its own s(x) (or one shared s),
+    advanced one after another by vofl_cnfp_step; every solve against the
+    oracle run on its own."""
+    L = 32.0 if len(shape) == 1 else 8.0   # h = 1/4 in 1D: FFT rounding amplified by |mu_max|^{2s} stays small
+    lo = (-L,) * len(shape)
+    hi = (L,) * len(shape)
+    X = mesh(shape, lo, hi)
+    ss = [1.0 + a * np.sin(np.pi * X[0] / 8) * (np.cos(np.pi * X[-1] / 8) if len(shape) > 1 else 1.0)
+          for a in (0.3, -0.2, 0.1)]
+    if not per_solve:
+        ss = [ss[0]] * 3
+    phis = [gaussian_pulse(shape, lo, hi, [c] * len(shape)) for c in (0.0, 1.0, -1.5)]
+    dt, M, steps = 5e-3, 8, 6
+    say(f"cnfp batch 3 {shape} per_solve={per_solve} {precision}")
+    p = _plan(shape, lo, hi, precision, s=np.stack(ss) if per_solve else ss[0], kappa=0.8, lam=0.4, M=M, dt=dt,
+              batch=3, coef_per_solve=per_solve)
+    up, u, its = _run(p, np.stack(phis), np.zeros((3,) + shape), precision, steps,
+                      1e-14 if precision == "fp64" else 1e-6)
+    hu = host(u).reshape((3,) + shape)
+    hp = host(up).reshape((3,) + shape)
+    for b in range(3):
+        rp, ru = O.cnfp_generic(as_seen(phis[b], precision), np.zeros(shape), ss[b], 0.8, lo, hi, M, dt, steps,
+                                f=lambda w: 0.4 * w ** 3)
+        eu, ep = rel_l2(hu[b], ru), rel_l2(hp[b], rp)
+        say(f"  solve {b}: rel L2 u {eu:.2e} u_prev {ep:.2e}")
+        assert eu <= tol(precision) and ep <= tol(precision)
+    say(f"  BiCGSTAB iterations (all solves) {its}")
