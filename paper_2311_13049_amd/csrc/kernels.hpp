@@ -513,12 +513,24 @@ __device__ __forceinline__ int c2r_nslots(int mode, int M) {
     }
 }
 
+// Tile of workgroup b when adjacent tiles should share an XCD's L2:
+// workgroups are dispatched to the 8 XCDs in turn (b mod 8), so b and b + 8
+// land on the same XCD and are given the neighbouring tiles 2j and 2j + 1 of
+// a group of 16; a last partial group keeps the identity order.
+__device__ __forceinline__ int xcd_pair_tile(int b, int nb) {
+    const int g = b / 16, r = b % 16;
+    if ((g + 1) * 16 > nb) return b;
+    return g * 16 + (r % 8) * 2 + r / 8;
+}
+
 // PD: slot pairs kept in flight (loaded into registers PD transforms ahead).
 // PAIRED: each stored row is loaded once. Pencil positions t and TP - t hold
 // each other's mirror rows (N - (t + TP e) = (TP - t) + TP (E-1-e)), so they
 // are placed in the same wavefront, W lanes apart, and swap their loaded
 // rows with lane shuffles; t = 0 and t = TP/2 are their own mirrors.
-template <typename T, int N, int E, int W, int MODE, int WPE, int PD = 1, bool PAIRED = false>
+// XCD: tiles ordered by xcd_pair_tile (half-width tiles whose rows share
+// cache lines with the neighbouring tile).
+template <typename T, int N, int E, int W, int MODE, int WPE, int PD = 1, bool PAIRED = false, bool XCD = false>
 __global__ __launch_bounds__(W*(N / E)) __attribute__((amdgpu_waves_per_eu(WPE)))
 void k_c2r0(C2RArgs<T> a) {
     static_assert(MODE >= 0 && MODE <= 3, "mode");
@@ -536,7 +548,8 @@ void k_c2r0(C2RArgs<T> a) {
     const int pr = int(threadIdx.x / 64) * (TW / 2) + jw / 2;  // PAIRED: pair index
     const int c = PAIRED ? lane % W : threadIdx.x % W;
     const int t = PAIRED ? ((jw % 2 == 0) ? pr : (pr == 0 ? TP / 2 : TP - pr)) : threadIdx.x / W;
-    const int col = blockIdx.x * W + c;
+    const int tile = XCD ? xcd_pair_tile(blockIdx.x, gridDim.x) : int(blockIdx.x);
+    const int col = tile * W + c;
     const bool active = col < a.inner;
     const int colc = active ? col : 0;
     const int item = blockIdx.y;

@@ -989,7 +989,7 @@ int autotune(vofl_plan_s* p, int steps) {
     if (e == hipSuccess) e = hipEventCreate(&e1);
     int rc = (e == hipSuccess) ? VOFL_OK : hip_fail(e, "autotune setup");
     std::vector<int> c2r, mid;
-    for (int c : {0, 2, 5, 6, 11, 12})
+    for (int c : {0, 2, 5, 6, 11, 12, 13})
         if (Launch<T>::c2r_variant_exists(g.n[0], c)) c2r.push_back(c);
     mid.push_back(0);
     if (g.ndim == 3)

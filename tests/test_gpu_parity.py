@@ -285,10 +285,11 @@ VARIANT_CASES = [
     ((64, 8, 48), (-4.0, -1.0, -3.0), (4.0, 1.0, 3.0)),   # 3D, 384 columns
     ((128, 8), (-8.0, -1.0), (8.0, 1.0)),                 # 2D, fewer columns than a tile
     ((256, 8, 16), (-16.0, -1.0, -2.0), (16.0, 1.0, 2.0)),  # axis 0 of the 256^3 workload
+    ((64, 1000), (-4.0, -62.5), (4.0, 62.5)),             # 1000 columns: a partial last tile group
 ]
 
 
-@pytest.mark.parametrize("variant", [0, 2, 5, 6, 11, 12])
+@pytest.mark.parametrize("variant", [0, 2, 5, 6, 11, 12, 13])
 @pytest.mark.parametrize("precision", ["fp64", "fp32"])
 @pytest.mark.parametrize("case", range(len(VARIANT_CASES)))
 def test_axis0_variants_apply_and_step(case, precision, variant):
