@@ -79,6 +79,8 @@ def main():
     ap.add_argument("--M", type=int, default=16)
     ap.add_argument("--precision", default="fp32")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="c3: skip the step-time spread and the b = 1, 4 apply rates (profiling runs)")
     ap.add_argument("--workload", default="c3", choices=("c3", "c4", "c5", "lffp", "ex3"))
     ap.add_argument("--requests", type=int, default=40, help="c5: requests in the trace")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -121,7 +123,7 @@ def main():
     elt = 4 if prec == "fp32" else 8
     tdt = torch.float32 if prec == "fp32" else torch.float64
     plan = V.Plan(c["shape"], c["lo"], c["hi"], Q=c["Q"], M=M, dt=c["dt"], precision=prec,
-                  c0=c["c0"], omega0=c["omega0"], max_batch=2)
+                  c0=c["c0"], omega0=c["omega0"], max_batch=4)
     u = torch.from_numpy(c["u0"]).to(dev, tdt)
     v = torch.from_numpy(c["v0"]).to(dev, tdt)
 
@@ -157,19 +159,38 @@ def main():
         if tr.get("source_hash") == kernel_source_hash():
             traffic = tr.get("bytes_per_launch")
 
-    # apply-only throughput (b = 2 fields, the L1/L2 pair size), same plan
-    ub = torch.stack([u, v]).contiguous()
-    ob = torch.empty_like(ub)
-    for _ in range(3):
-        plan.apply(V.VOFL_OP_S1, ub, ob)
-    torch.cuda.synchronize()
-    reps = 20
-    t0 = time.perf_counter()
-    for _ in range(reps):
-        plan.apply(V.VOFL_OP_S1, ub, ob)
-    torch.cuda.synchronize()
-    apply_s = (time.perf_counter() - t0) / reps
-    apply_rate = 2.0 / apply_s
+    # spread of the per-step time (after the timed region): 20 chunks of 10
+    # steps, each bracketed by HIP events on the stream the plan launches on
+    spread = None
+    if not args.no_extras:
+        chunk, nchunks = 10, 20
+        evs = [torch.cuda.Event(enable_timing=True) for _ in range(nchunks + 1)]
+        evs[0].record()
+        for i in range(nchunks):
+            plan.step(u, v, chunk)
+            evs[i + 1].record()
+        torch.cuda.synchronize()
+        per_step = sorted(evs[i].elapsed_time(evs[i + 1]) / chunk for i in range(nchunks))
+        spread = {"chunk_steps": chunk, "chunks": nchunks, "median_ms_per_step": float(np.median(per_step)),
+                  "p99_ms_per_step": float(np.percentile(per_step, 99)), "min_ms_per_step": per_step[0],
+                  "max_ms_per_step": per_step[-1]}
+
+    # apply-only throughput for b = 1, 2 (the L1/L2 pair size) and 4 fields, same plan
+    apply_rates = {}
+    for b in ((2,) if args.no_extras else (1, 2, 4)):
+        ub = torch.stack([u, v] * 2)[:b].contiguous()
+        ob = torch.empty_like(ub)
+        for _ in range(3):
+            plan.apply(V.VOFL_OP_S1, ub, ob)
+        torch.cuda.synchronize()
+        reps = 20
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            plan.apply(V.VOFL_OP_S1, ub, ob)
+        torch.cuda.synchronize()
+        apply_rates[b] = b / ((time.perf_counter() - t0) / reps)
+        del ub, ob
+    apply_rate = apply_rates[2]
 
     cpu = None
     if not args.no_cpu:
@@ -200,6 +221,8 @@ def main():
                    "grid": [n, n, n], "M": M, "precision": prec, "solver": "TSFP2 (3.13)"},
         "gpts_M_per_s": N * M * applies_per_s / 1e9,
         "apply_only_b2": {"applies_per_s": apply_rate, "gpts_M_per_s": N * M * apply_rate / 1e9},
+        "apply_only": {f"b{b}": {"applies_per_s": r, "gpts_M_per_s": N * M * r / 1e9} for b, r in apply_rates.items()},
+        "step_time_spread": spread,
         "roofline": {"bound": "hbm", "kernel": dom_name, "achieved": achieved, "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": (achieved / HBM_PEAK_GBS) if achieved else None,
                      "traffic": traffic, "alg_bytes_per_launch": alg,
