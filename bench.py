@@ -106,8 +106,19 @@ def main():
         for _ in range(5):
             b.copy_(a)
         torch.cuda.synchronize()
+        # achieved rate of a plain device copy (the practical HBM ceiling for
+        # a read + write stream on this GPU), HIP events on the current stream
+        reps = 20
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            b.copy_(a)
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / reps
         print(json.dumps({"copy_bytes_read_per_launch": nbytes, "copy_bytes_written_per_launch": nbytes,
-                          "launches": 5}), flush=True)
+                          "launches": 5 + reps, "copy_ms": ms, "copy_GBps_read_plus_write": 2 * nbytes / ms / 1e6}),
+              flush=True)
         return
     if args.workload == "c4":
         return bench_c4(args, torch, V, dev)
