@@ -203,7 +203,25 @@ def main():
         del ub, ob
     apply_rate = apply_rates[2]
 
+    # comparator: the plain FP64 path (FP64 plan, same workload, eager steps)
+    fp64_cmp = None
+    if not args.no_extras and prec == "fp32":
+        p64 = V.Plan(c["shape"], c["lo"], c["hi"], Q=c["Q"], M=M, dt=c["dt"], precision="fp64",
+                     c0=c["c0"], omega0=c["omega0"])
+        u64 = torch.from_numpy(c["u0"]).to(dev, torch.float64)
+        v64 = torch.from_numpy(c["v0"]).to(dev, torch.float64)
+        p64.step(u64, v64, 2)
+        torch.cuda.synchronize()
+        k64 = 10
+        t0 = time.perf_counter()
+        p64.step(u64, v64, k64)
+        torch.cuda.synchronize()
+        s64 = (time.perf_counter() - t0) / k64
+        fp64_cmp = {"ms_per_step": s64 * 1e3, "applies_per_s": 2.0 / s64, "steps": k64, "status": p64.sync_status()}
+        del p64, u64, v64
+
     cpu = None
+    cpu_mt = None
     if not args.no_cpu:
         import oracle as O
         gamma = O.gamma_from_Q(c["Q"])
@@ -214,6 +232,17 @@ def main():
         cpu = {"value": 1.0 / cpu_s, "unit": "applies/s", "cores": 1, "kind": "oracle",
                "sample": f"one oracle apply (2.13) of L1 on the {n}^3 M={M} field, FP64 numpy "
                          f"(pocketfft, single thread): {cpu_s:.1f} s"}
+        if not args.no_extras:
+            workers = max(1, min(16, int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))))
+            O.set_fft_workers(workers)
+            try:
+                t0 = time.perf_counter()
+                O.mterm_apply(x, 1.0 + gamma, c["lo"], c["hi"], M)
+                mt_s = time.perf_counter() - t0
+            finally:
+                O.set_fft_workers(0)
+            cpu_mt = {"value": 1.0 / mt_s, "unit": "applies/s", "cores": workers, "kind": "oracle",
+                      "sample": f"the same apply with scipy.fft on {workers} worker threads: {mt_s:.1f} s"}
 
     out = {
         "metric": "variable-order applies/s at 256^3, M=16 (two operator applies per TSFP2 step)",
@@ -240,7 +269,9 @@ def main():
                      "avg_launch_ms": avg_s * 1e3},
         "kernel_ms_per_step": {k: ms / args.steps for k, (ms, _) in ktimes.items()},
         "status": status,
+        "fp64_path": fp64_cmp,
         "cpu_baseline": cpu,
+        "cpu_oracle_multicore": cpu_mt,
     }
     print(json.dumps(out), flush=True)
 
