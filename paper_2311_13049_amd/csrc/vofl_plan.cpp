@@ -49,7 +49,7 @@ int hip_fail(hipError_t e, const char* what) {
 }
 
 // Sizes derived from a validated descriptor (no device access).
-// Crank-Nicolson solver storage (generic model, batch 1): vectors of N
+// Crank-Nicolson solver storage (generic model, one solve at a time): vectors of N
 // values in the plan precision and FP64 reduction scalars
 constexpr int CN_VECTORS = 11;
 constexpr int CN_SCALARS = 2 * 512 + 8;
@@ -789,7 +789,7 @@ int apply_any(vofl_plan_s* p, int op, const void* u, void* out, int nf, hipStrea
     return VOFL_OK;
 }
 
-// Crank-Nicolson scheme (3.2) for the generic model, batch 1: per step,
+// Crank-Nicolson scheme (3.2) for one solve of the generic model: per step,
 // w = u^{n+1} solves w + a L w - b f(w) = r with
 // r = 2 u^n - u^{n-1} - a L u^{n-1} + b f(u^{n-1}), a = kappa dt^2/2,
 // b = dt^2/2, f(w) = lambda w^3; fixed-point iteration on f(w), each linear
