@@ -340,10 +340,18 @@ class Plan:
         return vofl_cnfp_step(self.handle, u_prev.data_ptr(), u.data_ptr(), int(nsteps), tol, max_iter,
                               self._stream())
 
-    def solve(self, u0, v0, nsteps: int):
-        u = u0.clone()
-        v = v0.clone()
-        return self.step(u, v, nsteps)
+    def solve(self, u0, v0, nsteps: int, u=None, v=None):
+        """vofl_solve: (u, v) = (u0, v0) advanced by nsteps; new tensors unless given
+        (u0 and v0 may be the outputs themselves)."""
+        self._check_tensor(u0, self.batch, "u0")
+        self._check_tensor(v0, self.batch, "v0")
+        u = self.torch.empty_like(u0) if u is None else u
+        v = self.torch.empty_like(v0) if v is None else v
+        self._check_tensor(u, self.batch, "u")
+        self._check_tensor(v, self.batch, "v")
+        vofl_solve(self.handle, u0.data_ptr(), v0.data_ptr(), int(nsteps), u.data_ptr(), v.data_ptr(),
+                   self._stream())
+        return u, v
 
     def sync_status(self) -> int:
         return vofl_sync_status(self.handle, self._stream())
