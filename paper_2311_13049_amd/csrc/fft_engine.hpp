@@ -106,6 +106,32 @@ __device__ __forceinline__ void dft5(cpx<T>* v) {
     v[3] = csub(m2, t2);
 }
 
+// 10-point DFT from two 5-point DFTs of the even and odd samples:
+// X_k = E_k + w^k O_k, X_{k+5} = E_k - w^k O_k (k < 5), w = exp(s 2 pi i/10),
+// s = DIR (the sign of the exponent)
+template <int DIR, typename T>
+__device__ __forceinline__ void dft10(cpx<T>* v) {
+    cpx<T> e[5] = {v[0], v[2], v[4], v[6], v[8]};
+    cpx<T> o[5] = {v[1], v[3], v[5], v[7], v[9]};
+    dft5<DIR>(e);
+    dft5<DIR>(o);
+    // cos and sin of k pi/5, k = 1..4
+    const T c[4] = {T(0.80901699437494742410), T(0.30901699437494742410), T(-0.30901699437494742410),
+                    T(-0.80901699437494742410)};
+    const T sn[4] = {T(0.58778525229247312917), T(0.95105651629515357212), T(0.95105651629515357212),
+                     T(0.58778525229247312917)};
+#pragma unroll
+    for (int k = 1; k < 5; ++k) {
+        const T ss = DIR < 0 ? -sn[k - 1] : sn[k - 1];
+        o[k] = {o[k].x * c[k - 1] - o[k].y * ss, o[k].x * ss + o[k].y * c[k - 1]};
+    }
+#pragma unroll
+    for (int k = 0; k < 5; ++k) {
+        v[k] = cadd(e[k], o[k]);
+        v[k + 5] = csub(e[k], o[k]);
+    }
+}
+
 template <int DIR, typename T>
 __device__ __forceinline__ void dft4(cpx<T>* v) {
     cpx<T> a0 = cadd(v[0], v[2]);
@@ -190,15 +216,17 @@ __device__ __forceinline__ void dft(cpx<T>* v) {
     else if constexpr (R == 3) dft3<DIR>(v);
     else if constexpr (R == 4) dft4<DIR>(v);
     else if constexpr (R == 5) dft5<DIR>(v);
+    else if constexpr (R == 10) dft10<DIR>(v);
     else if constexpr (R == 8) dft8<DIR>(v);
     else if constexpr (R == 16) dft16<DIR>(v);
     else static_assert(R == 1, "unsupported radix");
 }
 
-// radix of the next stage: the first of 16, 8, 5, 4, 3, 2 dividing both the
-// remaining length and E
+// radix of the next stage: the first of 16, 10, 8, 5, 4, 3, 2 dividing both
+// the remaining length and E
 constexpr int pick_radix(int rem, int E) {
     return (rem % 16 == 0 && E % 16 == 0) ? 16
+         : (rem % 10 == 0 && E % 10 == 0) ? 10
          : (rem % 8 == 0 && E % 8 == 0)   ? 8
          : (rem % 5 == 0 && E % 5 == 0)   ? 5
          : (rem % 4 == 0 && E % 4 == 0)   ? 4
