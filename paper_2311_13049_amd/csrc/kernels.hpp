@@ -44,6 +44,30 @@ struct SolveScalars {
 };
 
 // ---------------------------------------------------------------------------
+// workgroup-to-tile order
+// ---------------------------------------------------------------------------
+// Workgroups are dispatched to the 8 XCDs in turn (b mod 8), each XCD with
+// its own L2. Tiles whose rows are shorter than a 128-byte line share every
+// line with their neighbours; xcd_group_tile gives workgroups b, b + 8, ...,
+// b + 8(G-1) (one XCD) the G neighbouring tiles Gj .. Gj + G - 1 of a group
+// of 8G, so each line is fetched into one L2 only. A last partial group
+// keeps the identity order. The map is a permutation of [0, nb).
+template <int G>
+__device__ __forceinline__ int xcd_group_tile(int b, int nb) {
+    if constexpr (G <= 1) {
+        return b;
+    } else {
+        const int span = 8 * G, g = b / span, r = b % span;
+        if ((g + 1) * span > nb) return b;
+        return g * span + (r % 8) * G + r / 8;
+    }
+}
+// tiles per 128-byte line for tile rows of W elements of B bytes
+constexpr int line_group(int W, int B) {
+    return (W * B >= 128) ? 1 : ((128 / (W * B)) > 8 ? 8 : 128 / (W * B));
+}
+
+// ---------------------------------------------------------------------------
 // pointwise helpers (FP64)
 // ---------------------------------------------------------------------------
 
@@ -360,8 +384,9 @@ __global__ __launch_bounds__(W*(N / E)) void k_mid(MidArgs<T> a) {
     const int c = threadIdx.x % W;
     const int t = threadIdx.x / W;
     const int tiles = (a.n2 + W - 1) / W;
-    const int plane = blockIdx.x / tiles;
-    const int col = (blockIdx.x % tiles) * W + c;
+    const int bl = xcd_group_tile<line_group(W, int(sizeof(cpx<T>)))>(blockIdx.x, gridDim.x);
+    const int plane = bl / tiles;
+    const int col = (bl % tiles) * W + c;
     const bool active = col < a.n2;
     const int colc = active ? col : 0;
     const int item = blockIdx.y / a.nf;
@@ -404,7 +429,7 @@ __global__ __launch_bounds__(W*(N / E)) void k_r2c0(R2CArgs<TR> a) {
     stage_twiddles<double, N>(tw_s, a.tw);
     const int c = threadIdx.x % W;
     const int t = threadIdx.x / W;
-    const int col = blockIdx.x * W + c;
+    const int col = xcd_group_tile<line_group(W, int(sizeof(TR)))>(blockIdx.x, gridDim.x) * W + c;
     const bool active = col < a.inner;
     const int colc = active ? col : 0;
     const int item = blockIdx.y;
@@ -513,24 +538,12 @@ __device__ __forceinline__ int c2r_nslots(int mode, int M) {
     }
 }
 
-// Tile of workgroup b when adjacent tiles should share an XCD's L2:
-// workgroups are dispatched to the 8 XCDs in turn (b mod 8), so b and b + 8
-// land on the same XCD and are given the neighbouring tiles 2j and 2j + 1 of
-// a group of 16; a last partial group keeps the identity order.
-__device__ __forceinline__ int xcd_pair_tile(int b, int nb) {
-    const int g = b / 16, r = b % 16;
-    if ((g + 1) * 16 > nb) return b;
-    return g * 16 + (r % 8) * 2 + r / 8;
-}
-
 // PD: slot pairs kept in flight (loaded into registers PD transforms ahead).
 // PAIRED: each stored row is loaded once. Pencil positions t and TP - t hold
 // each other's mirror rows (N - (t + TP e) = (TP - t) + TP (E-1-e)), so they
 // are placed in the same wavefront, W lanes apart, and swap their loaded
 // rows with lane shuffles; t = 0 and t = TP/2 are their own mirrors.
-// XCD: tiles ordered by xcd_pair_tile (half-width tiles whose rows share
-// cache lines with the neighbouring tile).
-template <typename T, int N, int E, int W, int MODE, int WPE, int PD = 1, bool PAIRED = false, bool XCD = false>
+template <typename T, int N, int E, int W, int MODE, int WPE, int PD = 1, bool PAIRED = false>
 __global__ __launch_bounds__(W*(N / E)) __attribute__((amdgpu_waves_per_eu(WPE)))
 void k_c2r0(C2RArgs<T> a) {
     static_assert(MODE >= 0 && MODE <= 3, "mode");
@@ -548,7 +561,7 @@ void k_c2r0(C2RArgs<T> a) {
     const int pr = int(threadIdx.x / 64) * (TW / 2) + jw / 2;  // PAIRED: pair index
     const int c = PAIRED ? lane % W : threadIdx.x % W;
     const int t = PAIRED ? ((jw % 2 == 0) ? pr : (pr == 0 ? TP / 2 : TP - pr)) : threadIdx.x / W;
-    const int tile = XCD ? xcd_pair_tile(blockIdx.x, gridDim.x) : int(blockIdx.x);
+    const int tile = xcd_group_tile<line_group(W, int(sizeof(cpx<T>)))>(blockIdx.x, gridDim.x);
     const int col = tile * W + c;
     const bool active = col < a.inner;
     const int colc = active ? col : 0;
@@ -907,7 +920,7 @@ __global__ __launch_bounds__(64 * NW_) void k_c2r0w(C2RArgs<T> a) {
     const int wv = threadIdx.x / 64, l = threadIdx.x % 64;
     const int cw = l % WV, t = l / WV;
     const int c = wv * WV + cw;                     // column within the tile
-    const int col0 = blockIdx.x * W;
+    const int col0 = xcd_group_tile<line_group(W, int(sizeof(cpx<T>)))>(blockIdx.x, gridDim.x) * W;
     const int col = col0 + c;
     const bool active = col < a.inner;
     const int colc = active ? col : 0;

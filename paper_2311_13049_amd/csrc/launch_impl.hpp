@@ -149,17 +149,15 @@ constexpr bool paired_ok() {
     return E % 2 == 0 && n / E >= 2 && W <= 32 && (64 / W) % 2 == 0 && ((n / E) * W) % 64 == 0;
 }
 
-template <typename T, int n, int E, int W, int WPE, int PD = 1, bool PAIRED = false, bool XCD = false>
+template <typename T, int n, int E, int W, int WPE, int PD = 1, bool PAIRED = false>
 hipError_t c2r0_mode(const C2RArgs<T>& a, int items, hipStream_t s) {
     const dim3 block(W * (n / E));
     const dim3 grid((a.inner + W - 1) / W, items);
     switch (a.mode) {
-        case C2R_APPLY: k_c2r0<T, n, E, W, C2R_APPLY, WPE, PD, PAIRED, XCD><<<grid, block, 0, s>>>(a); break;
-        case C2R_KICK: k_c2r0<T, n, E, W, C2R_KICK, WPE, PD, PAIRED, XCD><<<grid, block, 0, s>>>(a); break;
-        case C2R_EXPORT: k_c2r0<T, n, E, W, C2R_EXPORT, WPE, 1, PAIRED, XCD><<<grid, block, 0, s>>>(a); break;
-        case C2R_KICK_GENERIC:
-            k_c2r0<T, n, E, W, C2R_KICK_GENERIC, WPE, PD, PAIRED, XCD><<<grid, block, 0, s>>>(a);
-            break;
+        case C2R_APPLY: k_c2r0<T, n, E, W, C2R_APPLY, WPE, PD, PAIRED><<<grid, block, 0, s>>>(a); break;
+        case C2R_KICK: k_c2r0<T, n, E, W, C2R_KICK, WPE, PD, PAIRED><<<grid, block, 0, s>>>(a); break;
+        case C2R_EXPORT: k_c2r0<T, n, E, W, C2R_EXPORT, WPE, 1, PAIRED><<<grid, block, 0, s>>>(a); break;
+        case C2R_KICK_GENERIC: k_c2r0<T, n, E, W, C2R_KICK_GENERIC, WPE, PD, PAIRED><<<grid, block, 0, s>>>(a); break;
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
@@ -181,8 +179,8 @@ hipError_t c2r0w_mode(const C2RArgs<T>& a, int items, hipStream_t s) {
 // variants of the axis-0 kernel: 0 -> k_c2r0 (W columns, direct register
 // loads of rows min(k, N-k)); 2 -> k_c2r0 with W/2 columns; 11, 12 ->
 // k_c2r0 loading each stored row once (paired layout), with 1 and 2 slot
-// pairs in flight; 13 -> paired layout with W/2 columns, neighbouring tiles
-// on one XCD (xcd_pair_tile); 5 -> k_c2r0w (wave-local transforms, E = 8, 4 waves);
+// pairs in flight; 13 -> paired layout with W/2 columns; 5 -> k_c2r0w
+// (wave-local transforms, E = 8, 4 waves);
 // 6 -> k_c2r0w with 8 waves. A variant that does not exist for a length
 // (see c2r_variant_exists) falls back to variant 0; variants 5 and 6 also
 // fall back to 0 in the export mode.
@@ -195,7 +193,7 @@ hipError_t Launch<T>::c2r0(int N, const C2RArgs<T>& a, int items, hipStream_t s,
         constexpr int W2 = (W >= 8) ? W / 2 : W;                                        \
         if (variant == 2 && W2 != W) return c2r0_mode<T, n, E, W2, 1>(a, items, s);     \
         if constexpr (paired_ok<n, E, W2>() && W2 != W)                                  \
-            if (variant == 13) return c2r0_mode<T, n, E, W2, 1, 1, true, true>(a, items, s); \
+            if (variant == 13) return c2r0_mode<T, n, E, W2, 1, 1, true>(a, items, s);   \
         if constexpr (paired_ok<n, E, W>()) {                                           \
             if (variant == 11) return c2r0_mode<T, n, E, W, 1, 1, true>(a, items, s);   \
             if constexpr (sizeof(T) == 4 && E <= 8)                                       \
