@@ -543,17 +543,25 @@ __device__ __forceinline__ int c2r_nslots(int mode, int M) {
 // each other's mirror rows (N - (t + TP e) = (TP - t) + TP (E-1-e)), so they
 // are placed in the same wavefront, W lanes apart, and swap their loaded
 // rows with lane shuffles; t = 0 and t = TP/2 are their own mirrors.
-template <typename T, int N, int E, int W, int MODE, int WPE, int PD = 1, bool PAIRED = false>
+// STAGED: each stored row is loaded once, by one thread, into an LDS stage
+// (rows t + TP e for e < E/2 and the Nyquist row), and every thread reads
+// its rows min(k, N - k) from there; for lengths whose pencil positions
+// cannot be paired inside a wavefront.
+template <typename T, int N, int E, int W, int MODE, int WPE, int PD = 1, bool PAIRED = false,
+          bool STAGED = false>
 __global__ __launch_bounds__(W*(N / E)) __attribute__((amdgpu_waves_per_eu(WPE)))
 void k_c2r0(C2RArgs<T> a) {
     static_assert(MODE >= 0 && MODE <= 3, "mode");
     constexpr int TP = N / E;
     static_assert(!PAIRED || (E % 2 == 0 && TP >= 2 && W <= 32 && (64 / W) % 2 == 0 && (TP * W) % 64 == 0),
                   "paired layout needs pencil-position pairs inside a wavefront");
-    constexpr int NL = PAIRED ? E / 2 + 1 : E;  // rows loaded per slot and thread
+    static_assert(!(PAIRED && STAGED) && (!STAGED || E % 2 == 0), "staged layout");
+    constexpr int NL = (PAIRED || STAGED) ? E / 2 + 1 : E;  // rows loaded per slot and thread
+    constexpr int HR = N / 2 + 1;                            // stored rows
     // the paired variants also use a second FFT buffer (one barrier per exchange)
     __shared__ cpx<T> lds_fft[N * W];
     __shared__ cpx<T> lds_fft2[PAIRED ? N * W : 1];
+    __shared__ cpx<T> stg[STAGED ? 2 * HR * W : 1];
     __shared__ cpx<T> tw_s[N];
     stage_twiddles<T, N>(tw_s, a.tw);
     constexpr int TW = (W <= 64) ? 64 / W : 1;  // pencil positions per wavefront
@@ -592,7 +600,7 @@ void k_c2r0(C2RArgs<T> a) {
     // the plan); the slot base is uniform.
     unsigned roff[NL];
     auto row_off = [&](int e) __attribute__((always_inline)) -> unsigned {
-        if constexpr (PAIRED) {
+        if constexpr (PAIRED || STAGED) {
             // rows t + TP e for e < E/2, and the Nyquist row (used by t = 0
             // only; the other positions load the same cached row and drop it)
             const int r = (e == E / 2) ? N / 2 : t + TP * e;
@@ -663,6 +671,36 @@ void k_c2r0(C2RArgs<T> a) {
                 const T ax = pa.x, ay = edge ? T(0) : pa.y;
                 const T bx = two ? pb.x : T(0);
                 const T by = (two && !edge) ? pb.y : T(0);
+                y[e] = {lo ? ax - by : ax + by, lo ? ay + bx : bx - ay};
+            }
+            return;
+        }
+        if constexpr (STAGED) {
+            // the previous pair's stage reads are complete once every thread
+            // has passed an exchange barrier of its transform; a transform
+            // without an exchange needs a barrier here
+            if constexpr (num_stages(N, E) < 2) __syncthreads();
+#pragma unroll
+            for (int e = 0; e < E / 2; ++e) {
+                const int r = t + TP * e;
+                stg[r * W + c] = q1[e];
+                stg[(HR + r) * W + c] = q2[e];
+            }
+            if (t == 0) {
+                stg[(N / 2) * W + c] = q1[E / 2];
+                stg[(HR + N / 2) * W + c] = q2[E / 2];
+            }
+            __syncthreads();
+#pragma unroll
+            for (int e = 0; e < E; ++e) {
+                const int k = t + TP * e;
+                const int r = (k <= N / 2) ? k : N - k;
+                const cpx<T> u1 = stg[r * W + c], u2 = stg[(HR + r) * W + c];
+                const bool lo = k <= N / 2;
+                const bool edge = (k == 0) || (k == N / 2);
+                const T ax = u1.x, ay = edge ? T(0) : u1.y;
+                const T bx = two ? u2.x : T(0);
+                const T by = (two && !edge) ? u2.y : T(0);
                 y[e] = {lo ? ax - by : ax + by, lo ? ay + bx : bx - ay};
             }
             return;

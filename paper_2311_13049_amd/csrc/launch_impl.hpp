@@ -149,15 +149,17 @@ constexpr bool paired_ok() {
     return E % 2 == 0 && n / E >= 2 && W <= 32 && (64 / W) % 2 == 0 && ((n / E) * W) % 64 == 0;
 }
 
-template <typename T, int n, int E, int W, int WPE, int PD = 1, bool PAIRED = false>
+template <typename T, int n, int E, int W, int WPE, int PD = 1, bool PAIRED = false, bool STAGED = false>
 hipError_t c2r0_mode(const C2RArgs<T>& a, int items, hipStream_t s) {
     const dim3 block(W * (n / E));
     const dim3 grid((a.inner + W - 1) / W, items);
     switch (a.mode) {
-        case C2R_APPLY: k_c2r0<T, n, E, W, C2R_APPLY, WPE, PD, PAIRED><<<grid, block, 0, s>>>(a); break;
-        case C2R_KICK: k_c2r0<T, n, E, W, C2R_KICK, WPE, PD, PAIRED><<<grid, block, 0, s>>>(a); break;
-        case C2R_EXPORT: k_c2r0<T, n, E, W, C2R_EXPORT, WPE, 1, PAIRED><<<grid, block, 0, s>>>(a); break;
-        case C2R_KICK_GENERIC: k_c2r0<T, n, E, W, C2R_KICK_GENERIC, WPE, PD, PAIRED><<<grid, block, 0, s>>>(a); break;
+        case C2R_APPLY: k_c2r0<T, n, E, W, C2R_APPLY, WPE, PD, PAIRED, STAGED><<<grid, block, 0, s>>>(a); break;
+        case C2R_KICK: k_c2r0<T, n, E, W, C2R_KICK, WPE, PD, PAIRED, STAGED><<<grid, block, 0, s>>>(a); break;
+        case C2R_EXPORT: k_c2r0<T, n, E, W, C2R_EXPORT, WPE, 1, PAIRED, STAGED><<<grid, block, 0, s>>>(a); break;
+        case C2R_KICK_GENERIC:
+            k_c2r0<T, n, E, W, C2R_KICK_GENERIC, WPE, PD, PAIRED, STAGED><<<grid, block, 0, s>>>(a);
+            break;
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
@@ -179,8 +181,9 @@ hipError_t c2r0w_mode(const C2RArgs<T>& a, int items, hipStream_t s) {
 // variants of the axis-0 kernel: 0 -> k_c2r0 (W columns, direct register
 // loads of rows min(k, N-k)); 2 -> k_c2r0 with W/2 columns; 11, 12 ->
 // k_c2r0 loading each stored row once (paired layout), with 1 and 2 slot
-// pairs in flight; 13 -> paired layout with W/2 columns; 5 -> k_c2r0w
-// (wave-local transforms, E = 8, 4 waves);
+// pairs in flight; 13 -> paired layout with W/2 columns; 14 -> k_c2r0
+// staging each stored row once through LDS; 5 -> k_c2r0w (wave-local
+// transforms, E = 8, 4 waves);
 // 6 -> k_c2r0w with 8 waves. A variant that does not exist for a length
 // (see c2r_variant_exists) falls back to variant 0; variants 5 and 6 also
 // fall back to 0 in the export mode.
@@ -192,6 +195,8 @@ hipError_t Launch<T>::c2r0(int N, const C2RArgs<T>& a, int items, hipStream_t s,
         constexpr int W = c2r_width<T, n>(), E = e_c2r0(n);                             \
         constexpr int W2 = (W >= 8) ? W / 2 : W;                                        \
         if (variant == 2 && W2 != W) return c2r0_mode<T, n, E, W2, 1>(a, items, s);     \
+        if constexpr (E % 2 == 0)                                                       \
+            if (variant == 14) return c2r0_mode<T, n, E, W, 1, 1, false, true>(a, items, s); \
         if constexpr (paired_ok<n, E, W2>() && W2 != W)                                  \
             if (variant == 13) return c2r0_mode<T, n, E, W2, 1, 1, true>(a, items, s);   \
         if constexpr (paired_ok<n, E, W>()) {                                           \
@@ -222,6 +227,7 @@ bool Launch<T>::c2r_variant_exists(int N, int variant) {
         if (variant == 11) return paired_ok<n, E, W>();                                 \
         if (variant == 12) return paired_ok<n, E, W>() && sizeof(T) == 4 && E <= 8;     \
         if (variant == 13) return W >= 8 && paired_ok<n, E, (W >= 8 ? W / 2 : W)>();    \
+        if (variant == 14) return E % 2 == 0;                                           \
         if (variant == 5) return C2RW<T, n, 8, 4>::ok && sizeof(T) == 4;                \
         if (variant == 6) return C2RW<T, n, 8, 8>::ok && sizeof(T) == 4;                \
         return false;                                                                   \

@@ -989,7 +989,7 @@ int autotune(vofl_plan_s* p, int steps) {
     if (e == hipSuccess) e = hipEventCreate(&e1);
     int rc = (e == hipSuccess) ? VOFL_OK : hip_fail(e, "autotune setup");
     std::vector<int> c2r, mid;
-    for (int c : {0, 2, 5, 6, 11, 12, 13})
+    for (int c : {0, 2, 5, 6, 11, 12, 13, 14})
         if (Launch<T>::c2r_variant_exists(g.n[0], c)) c2r.push_back(c);
     mid.push_back(0);
     if (g.ndim == 3)
@@ -1146,12 +1146,14 @@ int vofl_plan(const vofl_desc* d, void* stream, vofl_plan_t* out) {
         p->w1 = 1.0 / (2.0 - c);
         p->w0 = -c / (2.0 - c);
     }
-    // default axis-0 kernel: the paired layout (each stored row loaded once)
-    // where the length allows it
+    // default axis-0 kernel: each stored row loaded once, by the paired
+    // layout where the length allows it, else through the LDS stage
     if (g.ndim >= 2) {
-        const bool paired = (d->precision == VOFL_FP32) ? Launch<float>::c2r_variant_exists(g.n[0], 11)
-                                                        : Launch<double>::c2r_variant_exists(g.n[0], 11);
-        p->c2r_variant = paired ? 11 : 0;
+        auto exists = [&](int v) {
+            return (d->precision == VOFL_FP32) ? Launch<float>::c2r_variant_exists(g.n[0], v)
+                                               : Launch<double>::c2r_variant_exists(g.n[0], v);
+        };
+        p->c2r_variant = exists(11) ? 11 : exists(14) ? 14 : 0;
     }
     if (const char* ev = std::getenv("VOFL_C2R_VARIANT")) p->c2r_variant = std::atoi(ev);
     if (const char* ev = std::getenv("VOFL_MID_VARIANT")) p->mid_variant = std::atoi(ev);

@@ -202,7 +202,7 @@ def test_autotuned_plans_pick_listed_variants_and_stay_accurate(c4, tmp_path):
             say(f"autotune {shots[0]['shape']} x {len(shots)}")
             p = _plan(c4, shots, not big, tune_steps=3)
             info = p.info()
-            assert info["c2r_variant"] in (0, 2, 5, 6, 11, 12, 13)
+            assert info["c2r_variant"] in (0, 2, 5, 6, 11, 12, 13, 14)
             q = _plan(c4, shots, not big, tune_steps=3)  # served from the cache file
             assert q.info()["c2r_variant"] == info["c2r_variant"]
             u, v = _fields(shots)

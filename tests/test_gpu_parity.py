@@ -289,7 +289,7 @@ VARIANT_CASES = [
 ]
 
 
-@pytest.mark.parametrize("variant", [0, 2, 5, 6, 11, 12, 13])
+@pytest.mark.parametrize("variant", [0, 2, 5, 6, 11, 12, 13, 14])
 @pytest.mark.parametrize("precision", ["fp64", "fp32"])
 @pytest.mark.parametrize("case", range(len(VARIANT_CASES)))
 def test_axis0_variants_apply_and_step(case, precision, variant):
