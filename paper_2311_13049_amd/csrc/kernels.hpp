@@ -569,7 +569,8 @@ void k_c2r0(C2RArgs<T> a) {
     const int pr = int(threadIdx.x / 64) * (TW / 2) + jw / 2;  // PAIRED: pair index
     const int c = PAIRED ? lane % W : threadIdx.x % W;
     const int t = PAIRED ? ((jw % 2 == 0) ? pr : (pr == 0 ? TP / 2 : TP - pr)) : threadIdx.x / W;
-    const int tile = xcd_group_tile<line_group(W, int(sizeof(cpx<T>)))>(blockIdx.x, gridDim.x);
+    // grouped by the narrowest per-point array read (A, B in the plan precision)
+    const int tile = xcd_group_tile<line_group(W, int(sizeof(T)))>(blockIdx.x, gridDim.x);
     const int col = tile * W + c;
     const bool active = col < a.inner;
     const int colc = active ? col : 0;
