@@ -470,11 +470,11 @@ def bench_ex3(args, torch, V, dev):
     del pb, ub_prev, ub, phi2
     elt = 4 if prec == "fp32" else 8
     H = (n // 2 + 1) * n
-    # algorithmic bytes per step (read + write once): difference quotient
-    # (2 FP64 fields in, 1 out), two FP64 forward axis-0 passes, the last-axis
+    # algorithmic bytes per step (read + write once): two FP64 forward axis-0
+    # passes (u; w formed from u^n and u^{n-1} while loading), the last-axis
     # pass (2 FP64 half spectra in, 2(M+1) term slots out) and the axis-0
     # update pass (2(M+1) slots, delta, A, B, FP64 state in and out)
-    alg = {"lffp_w": 24 * N, "r2c0": 2 * (8 * N + 16 * H), "contig_lffp": 2 * 16 * H + 2 * (M + 1) * H * 2 * elt,
+    alg = {"r2c0": 24 * N + 2 * 16 * H, "contig_lffp": 2 * 16 * H + 2 * (M + 1) * H * 2 * elt,
            "c2r0_lffp": 2 * (M + 1) * H * 2 * elt + 8 * N + 2 * elt * N + 32 * N}
     per_step = {k: ms / 3 for k, (ms, _) in kt.items()}
     c2r_ms = kt["c2r0_lffp"][0] / kt["c2r0_lffp"][1] if "c2r0_lffp" in kt else None  # per launch

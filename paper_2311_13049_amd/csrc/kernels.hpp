@@ -411,6 +411,8 @@ __global__ __launch_bounds__(W*(N / E)) void k_mid(MidArgs<T> a) {
 template <typename TR>
 struct R2CArgs {
     const TR* in;           // real fields: item b at in + b*Nreal
+    const TR* in2;          // optional second fields: the input is c1 in + c2 in2 (FP64)
+    double c1, c2;
     long long Nreal;
     cpx<double>* out;       // FP64 half spectra: item b at out + b*H
     long long H;
@@ -438,6 +440,11 @@ __global__ __launch_bounds__(W*(N / E)) void k_r2c0(R2CArgs<TR> a) {
     cpx<double> v[E];
 #pragma unroll
     for (int e = 0; e < E; ++e) v[e] = {double(src[(long long)(t + TP * e) * a.inner]), 0.0};
+    if (a.in2) {  // uniform: a combination of two fields, formed in FP64 while loading
+        const TR* src2 = a.in2 + (long long)item * a.Nreal + colc;
+#pragma unroll
+        for (int e = 0; e < E; ++e) v[e].x = a.c1 * v[e].x + a.c2 * double(src2[(long long)(t + TP * e) * a.inner]);
+    }
     fft_pencil<double, N, E, -1>(v, t, lds, tw_s);
     if (active) {
         cpx<double>* dst = a.out + (long long)item * a.H + colc;

@@ -73,8 +73,8 @@ struct Geometry {
 
 bool is_fp32(const vofl_desc* d) { return d->precision == VOFL_FP32; }
 
-// FP64 fields of the leap-frog state per solve (2D/3D plans)
-int lffp_fields(int model) { return model == VOFL_MODEL_SEISMIC ? 3 : 2; }
+// FP64 fields of the leap-frog state per solve (2D/3D plans): u^{n-1}, u^n
+int lffp_fields(int) { return 2; }
 
 bool supported_len(int ndim, int n, bool fp32) {
     if (ndim == 1) return fp32 ? Launch<float>::supported_1d(n) : Launch<double>::supported_1d(n);
@@ -174,7 +174,7 @@ int derive(const vofl_desc* d, Geometry& g) {
         bytes += (size_t)slots * g.H * celt;                  // work slots
         g.stage_fields = std::max(2 * g.batch, g.max_batch);
         bytes += (size_t)g.stage_fields * g.H * 16;           // FP64 state / forward staging
-        // FP64 leap-frog state (u^{n-1}, u^n; for (1.1) also the difference quotient w)
+        // FP64 leap-frog state (u^{n-1}, u^n)
         bytes += (size_t)lffp_fields(d->model) * g.batch * g.Nreal * 8;
     }
     if (d->model == VOFL_MODEL_GENERIC)
@@ -214,7 +214,6 @@ struct vofl_plan_s {
     cpx<double>* tw64[3] = {nullptr, nullptr, nullptr};
     double* delta = nullptr;
     double* LS = nullptr;              // leap-frog FP64 state: u^{n-1} of every solve, then u^n
-                                       // (seismic model: then w, the difference quotient)
     void* cnv = nullptr;               // Crank-Nicolson vectors (CN_VECTORS x N, one solve at a time)
     int coef_item = 0;                 // solve whose coefficients single-field launches use
                                        // (set by the Crank-Nicolson driver; else 0)
@@ -456,10 +455,14 @@ hipError_t mid(vofl_plan_s* p, const char* name, int dir, cpx<T>* buf, long long
 // forward transform of real fields (items of Nreal values) into the FP64
 // staging block at stage + item*H, including the 3D middle axis
 template <typename T>
-hipError_t forward_to_stage(vofl_plan_s* p, const T* in, cpx<double>* stage, int items, hipStream_t s) {
+hipError_t forward_to_stage(vofl_plan_s* p, const T* in, cpx<double>* stage, int items, hipStream_t s,
+                           const T* in2 = nullptr, double c1 = 1.0, double c2 = 0.0) {
     const Geometry& g = p->g;
     R2CArgs<T> r{};
     r.in = in;
+    r.in2 = in2;  // optional: transform c1 in + c2 in2
+    r.c1 = c1;
+    r.c2 = c2;
     r.Nreal = g.Nreal;
     r.out = stage;
     r.H = g.H;
@@ -564,9 +567,9 @@ int lffp_multi(vofl_plan_s* p, double cb0, double ca0, double cf0, double wc0, d
 
 
 
-// Leap-frog steps for (1.1) on the plan's FP64 state (u^{n-1}, u^n, w):
-// per step w = wc u^n + wp u^{n-1} ((u^n - u^{n-1})/dt; the first step uses
-// (wc0, wp0)), forward transforms of (u^n, w) in FP64, the 2(M+1) term
+// Leap-frog steps for (1.1) on the plan's FP64 state (u^{n-1}, u^n):
+// per step forward transforms in FP64 of u^n and of w = wc u^n + wp u^{n-1}
+// ((u^n - u^{n-1})/dt, formed while loading; the first step uses (wc0, wp0)), the 2(M+1) term
 // spectra l_m |mu|^{2 sigma_1} u_hat and l_m |mu|^{2 sigma_2} w_hat along the
 // last (and middle) axis, and the axis-0 pass that sums -A L1 u - B L2 w by
 // (2.13) and updates the state in place.
@@ -579,7 +582,6 @@ int lffp_seismic_multi(vofl_plan_s* p, double cb0, double ca0, double cf0, doubl
     const long long SS = (long long)g.step_slots * g.H;
     double* prev = p->LS;
     double* cur = p->LS + n;
-    double* wq = p->LS + 2 * n;
     cpx<T>* W = (cpx<T>*)p->work;
     cpx<double>* U = (cpx<double>*)p->U;
     cpx<double>* V = (cpx<double>*)p->V;
@@ -607,16 +609,11 @@ int lffp_seismic_multi(vofl_plan_s* p, double cb0, double ca0, double cf0, doubl
         c.lf_cb = k == 0 ? cb0 : 2.0;
         c.lf_ca = k == 0 ? ca0 : -1.0;
         c.lf_cf = k == 0 ? cf0 : p->dt * p->dt;
-        const double* w = prev;  // the start passes w = psi in the prev slot
-        if (!(wc == 0.0 && wp == 1.0)) {
-            e = p->timed("lffp_w", s, [&] {
-                return Launch<double>::lincomb(wq, cur, wc, prev, wp, nullptr, 0.0, nullptr, 0.0, n, s);
-            });
-            if (e != hipSuccess) return hip_fail(e, "difference quotient launch");
-            w = wq;
-        }
         if ((e = forward_to_stage<double>(p, cur, U, items, s)) != hipSuccess) return hip_fail(e, "r2c0 launch");
-        if ((e = forward_to_stage<double>(p, w, V, items, s)) != hipSuccess) return hip_fail(e, "r2c0 launch");
+        // w: the start passes psi itself in the prev slot
+        e = (wc == 0.0 && wp == 1.0) ? forward_to_stage<double>(p, prev, V, items, s)
+                                     : forward_to_stage<double>(p, cur, V, items, s, prev, wc, wp);
+        if (e != hipSuccess) return hip_fail(e, "r2c0 launch");
         if ((e = mid<double>(p, "mid_lffp_fwd", -1, U, g.H, 1, 2 * items, p->tw64[1 % g.ndim], s)) != hipSuccess)
             return hip_fail(e, "mid launch");
         e = p->timed("contig_lffp", s, [&] { return Launch<T>::contig(g.nlast, a, items, s); });

@@ -87,7 +87,7 @@ def test_valid_descriptors_and_footprint_formula():
     H = (n0 // 2 + 1) * n1
     slots = max(2 * (M + 1) + 3, 3 * (M + 1))
     expect = (n0 + n1) * (8 + 16 + 8) + 512 * (8 + 8) + 64 + 256 + slots * H * 8 + max(2, 3) * H * 16
-    expect += 3 * 512 * 8   # FP64 leap-frog state of (1.1): u^{n-1}, u^n and the difference quotient
+    expect += 2 * 512 * 8   # FP64 leap-frog state of (1.1): u^{n-1}, u^n
     assert b == expect
     # generic model: M + 2 step slots plus the FP64 leap-frog state (2 fields)
     d, keep = _desc(precision="fp32", max_batch=3, model="generic", gamma=None, s=np.full(512, 1.2), kappa=1.0)
