@@ -118,3 +118,14 @@ def test_plan_without_device_reports_device_error():
         assert e.code == V.VOFL_ERR_DEVICE
         return
     V.vofl_destroy(h)  # a GPU is present: the plan is valid
+
+
+def test_missing_library_fails_loudly(tmp_path, monkeypatch):
+    """There is no CPU fallback: without the built library every call raises."""
+    monkeypatch.setattr(V, "LIB_PATH", str(tmp_path / "absent" / "libvofl.so"))
+    monkeypatch.setattr(V, "_lib", None)
+    with pytest.raises(ImportError):
+        V.load_library()
+    d, keep = _desc()
+    with pytest.raises(ImportError):
+        V.vofl_plan_footprint(d)
