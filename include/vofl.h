@@ -110,7 +110,10 @@ typedef struct vofl_plan_s* vofl_plan_t;
  * VOFL_ERR_INVALID (bad descriptor), VOFL_ERR_UNSUPPORTED (no FFT length),
  * VOFL_ERR_NOMEM (allocation failed or footprint above hbm_budget),
  * VOFL_ERR_DEVICE (no HIP device). The descriptor and host arrays are not
- * retained. */
+ * retained. The environment variables VOFL_C2R_VARIANT (axis-0 kernel: 0, 2,
+ * 5, 6, 11, 12, 13, 14) and VOFL_MID_VARIANT (middle-axis tile: 0, 1, 2)
+ * force a kernel variant instead of the default (a variant without a kernel
+ * for the plan's length runs as variant 0); results agree to rounding. */
 int vofl_plan(const vofl_desc* desc, void* stream, vofl_plan_t* out);
 
 /* Device bytes a plan for desc would allocate (same validation as vofl_plan,
