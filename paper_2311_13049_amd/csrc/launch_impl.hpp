@@ -95,7 +95,7 @@ hipError_t Launch<T>::mid(int N, int dir, const MidArgs<T>& a, int planes, int i
         if (variant == 2 && W4 != W2) {                                                 \
             if (dir < 0) k_mid<T, n, E, W4, -1><<<grid, dim3(W4 * (n / E)), 0, s>>>(a); \
             else k_mid<T, n, E, W4, +1><<<grid, dim3(W4 * (n / E)), 0, s>>>(a);        \
-        } else if (variant >= 1 && W2 != W) {                                           \
+        } else if ((variant == 1 || variant == 2) && W2 != W) {                         \
             if (dir < 0) k_mid<T, n, E, W2, -1><<<grid, dim3(W2 * (n / E)), 0, s>>>(a); \
             else k_mid<T, n, E, W2, +1><<<grid, dim3(W2 * (n / E)), 0, s>>>(a);        \
         } else {                                                                        \

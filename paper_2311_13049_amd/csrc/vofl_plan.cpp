@@ -1153,7 +1153,11 @@ int vofl_plan(const vofl_desc* d, void* stream, vofl_plan_t* out) {
         p->c2r_variant = exists(11) ? 11 : exists(14) ? 14 : 0;
     }
     if (const char* ev = std::getenv("VOFL_C2R_VARIANT")) p->c2r_variant = std::atoi(ev);
-    if (const char* ev = std::getenv("VOFL_MID_VARIANT")) p->mid_variant = std::atoi(ev);
+    if (const char* ev = std::getenv("VOFL_MID_VARIANT")) {
+        // only 0, 1, 2 exist; the launcher's grid and kernel tile must agree
+        const int v = std::atoi(ev);
+        p->mid_variant = (v >= 0 && v <= 2) ? v : 0;
+    }
     rc = (d->precision == VOFL_FP32) ? upload_tables<float>(p, delta, A, B)
                                      : upload_tables<double>(p, delta, A, B);
     if (rc == VOFL_OK && d->tune_steps > 0)
