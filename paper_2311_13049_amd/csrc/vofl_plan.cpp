@@ -954,8 +954,8 @@ bool tune_cache_lookup(vofl_plan_s* p, const std::string& key) {
         int c = 0, m = 0;
         double ms = 0;
         if (rest >> c >> m >> ms) {
-            p->c2r_variant = c;
-            p->mid_variant = m;
+            p->c2r_variant = c;                    // a variant without a kernel runs as 0
+            p->mid_variant = (m >= 0 && m <= 2) ? m : 0;
             p->tuned_ms = ms;
             found = true;  // the last matching line wins
         }
