@@ -170,3 +170,40 @@ def test_unstable_step_sets_flag():
     up, u = p.lffp_start(dev(phi, "fp64"), dev(np.zeros(shape), "fp64"))
     p.lffp_step(up, u, 2000)
     assert p.sync_status() == V.VOFL_ERR_UNSTABLE
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_1d_batch_own_gamma_and_c0_vs_oracle(precision):
+    """1D, three solves with their own gamma and c0 fields in one kernel launch."""
+    n, lo, hi = 256, (-16.0,), (16.0,)
+    x = grid_1d(n, lo[0], hi[0])
+    gammas = [0.05 + 0.03 * np.sin(np.pi * x / 8.0 + k) for k in range(3)]
+    c0s = [1.0 + 0.2 * np.tanh(x - k) for k in range(3)]
+    phis = [np.exp(-(x - k) ** 2) for k in range(3)]
+    dt, M, steps = 1e-3, 8, 80
+    say(f"lffp seismic 1D batch 3 {precision}")
+    p = _plan((n,), lo, hi, precision, gamma=np.stack(gammas), c0_field=np.stack(c0s), omega0=1.2, M=M, dt=dt,
+              batch=3, coef_per_solve=True)
+    up, u = _run_gpu(p, np.stack(phis), np.zeros((3, n)), precision, steps)
+    u = u.reshape(3, n)
+    for b in range(3):
+        _, ru = O.lffp_seismic(as_seen(phis[b], precision), np.zeros(n), gammas[b], c0s[b], 1.2, lo, hi, M, dt,
+                               steps)
+        e = rel_l2(u[b], ru)
+        say(f"  solve {b}: rel L2 u {e:.2e}")
+        assert e <= tol(precision)
+
+
+def test_2d_radix3_grid_vs_oracle():
+    """768 x 96 (radix-3 lengths on both axes), layered medium, FP64."""
+    shape, lo, hi = (768, 96), (0.0, 0.0), (12.0, 1.5)
+    gamma, c0 = _layers(shape, lo, hi)
+    phi = ricker(shape, lo, hi, (6.0, 0.7), 2.0)
+    dt, M, steps = 2e-3, 6, 25
+    say("lffp seismic 2D 768 x 96 fp64")
+    p = _plan(shape, lo, hi, "fp64", gamma=gamma, c0_field=c0, M=M, dt=dt)
+    up, u = _run_gpu(p, phi, np.zeros(shape), "fp64", steps)
+    _, ru = O.lffp_seismic(phi, np.zeros(shape), gamma, c0, 1.0, lo, hi, M, dt, steps)
+    e = rel_l2(u.reshape(shape), ru)
+    say(f"  rel L2 u {e:.2e}")
+    assert e <= tol("fp64")
