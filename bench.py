@@ -81,7 +81,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-extras", action="store_true",
                     help="c3: skip the step-time spread and the b = 1, 4 apply rates (profiling runs)")
-    ap.add_argument("--workload", default="c3", choices=("c3", "c4", "c5", "lffp", "ex3"))
+    ap.add_argument("--workload", default="c3", choices=("c3", "c2", "c4", "c5", "lffp", "ex3"))
     ap.add_argument("--requests", type=int, default=40, help="c5: requests in the trace")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain device copy of 1 GiB five times (HBM counter calibration)")
@@ -128,6 +128,8 @@ def main():
         return bench_lffp(args, torch, V, dev)
     if args.workload == "ex3":
         return bench_ex3(args, torch, V, dev)
+    if args.workload == "c2":
+        return bench_c2(args, torch, V, dev)
     n, M = args.n, args.M
     c = c3_inputs(n=n)
     prec = args.precision
@@ -424,6 +426,72 @@ def bench_lffp(args, torch, V, dev):
         "roofline_c2r0_lffp": {"bound": "hbm", "achieved": alg_c2r / (c2r_ms / c2r_n / 1e3) / 1e9 if c2r_ms else None,
                                "peak": HBM_PEAK_GBS, "unit": "GB/s", "alg_bytes_per_launch": alg_c2r},
         "status": plan.sync_status(),
+    }
+    print(json.dumps(out), flush=True)
+
+
+def bench_c2(args, torch, V, dev):
+    """2D workload: 1024^2 on [-32,32)^2, GRF Q in [10, 200], M = 16, FP64
+    (the plain path the workload names), dt = 5e-4; TSFP2 steps and the
+    apply of two fields; the FP32 form of the same run beside it."""
+    from workloads import c2_inputs
+    c = c2_inputs()
+    n, M = c["shape"][0], c["M"]
+
+    def run(prec):
+        tdt = torch.float64 if prec == "fp64" else torch.float32
+        plan = V.Plan(c["shape"], c["lo"], c["hi"], Q=c["Q"], M=M, dt=c["dt"], precision=prec, c0=c["c0"],
+                      omega0=c["omega0"], max_batch=2)
+        u = torch.from_numpy(c["u0"]).to(dev, tdt)
+        v = torch.from_numpy(c["v0"]).to(dev, tdt)
+        plan.step(u, v, args.warmup)
+        torch.cuda.synchronize()
+        plan.set_timing(True)
+        t0 = time.perf_counter()
+        plan.step(u, v, args.steps)
+        torch.cuda.synchronize()
+        step_s = (time.perf_counter() - t0) / args.steps
+        kt = plan.kernel_times()
+        plan.set_timing(False)
+        status = plan.sync_status()
+        ub = torch.stack([u, v]).contiguous()
+        ob = torch.empty_like(ub)
+        plan.apply(V.VOFL_OP_S1, ub, ob)
+        torch.cuda.synchronize()
+        reps = 50
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            plan.apply(V.VOFL_OP_S1, ub, ob)
+        torch.cuda.synchronize()
+        return step_s, kt, (time.perf_counter() - t0) / reps, status
+
+    step_s, kt, apply_s, status = run("fp64")
+    step32, _, apply32, status32 = run("fp32")
+    elt = 8
+    N, H, cb = n * n, (n // 2 + 1) * n, 2 * elt
+    nterm = 2 * (M + 1)
+    # 2D: no middle axis; the kick's axis-0 pass and last-axis pass as in 3D
+    alg = {"c2r0_kick": nterm * H * cb + N * (8 + 2 * elt) + H * cb,
+           "contig_kick": H * cb + 4 * H * 16 + nterm * H * cb}
+    dom = max((k for k in alg if k in kt), key=lambda k: kt[k][0])
+    avg = kt[dom][0] / kt[dom][1] / 1e3
+    out = {
+        "metric": "variable-order applies/s at 1024^2, M=16, FP64 (two operator applies per TSFP2 step)",
+        "value": 2.0 / step_s, "unit": "applies/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": step_s * 1e3, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64", "data": "synthetic",
+        "config": {"workload": "2D periodic [-32,32)^2, 1024^2, M=16, GRF Q in [10,200] (corr. length 4), "
+                               "Gaussian pulse u0, v0 = 0, c0 = omega0 = 1, dt = 5e-4", "grid": [n, n], "M": M,
+                   "precision": "fp64"},
+        "gpts_M_per_s": N * M * 2.0 / step_s / 1e9,
+        "apply_only_b2": {"applies_per_s": 2.0 / apply_s, "ms_per_apply_of_two": apply_s * 1e3},
+        "kernel_ms_per_step": {k: ms / args.steps for k, (ms, _) in kt.items()},
+        "roofline": {"bound": "hbm", "kernel": dom, "achieved": alg[dom] / avg / 1e9, "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": alg[dom] / avg / 1e9 / HBM_PEAK_GBS, "traffic": None,
+                     "alg_bytes_per_launch": alg[dom], "avg_launch_ms": avg * 1e3},
+        "fp32_form": {"ms_per_step": step32 * 1e3, "applies_per_s": 2.0 / step32,
+                      "apply_only_b2_applies_per_s": 2.0 / apply32, "status": status32},
+        "status": status,
     }
     print(json.dumps(out), flush=True)
 
