@@ -14,7 +14,7 @@ namespace vofl {
 // (radix-5 and radix-2 stages, 100 threads per pencil).
 constexpr bool has3(int N) { return N % 3 == 0; }
 constexpr bool has5(int N) { return N % 5 == 0; }
-constexpr int e_contig(int N) { return has5(N) ? 10 : has3(N) ? 12 : (N < 8 ? N : 8); }
+constexpr int e_contig(int N) { return has5(N) ? 10 : has3(N) ? 12 : (N < 8 ? N : (N >= 1024 ? 4 : 8)); }
 constexpr int e_mid(int N) { return has5(N) ? 10 : has3(N) ? 12 : (N < 16 ? N : 16); }
 constexpr int e_r2c0(int N) { return has5(N) ? 10 : has3(N) ? 12 : (N < 16 ? N : 16); }
 constexpr int e_c2r0(int N) { return has5(N) ? 10 : has3(N) ? 12 : (N < 8 ? N : 8); }
