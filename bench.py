@@ -224,6 +224,7 @@ def main():
 
     cpu = None
     cpu_mt = None
+    accuracy = None
     if not args.no_cpu:
         import oracle as O
         gamma = O.gamma_from_Q(c["Q"])
@@ -234,6 +235,20 @@ def main():
         cpu = {"value": 1.0 / cpu_s, "unit": "applies/s", "cores": 1, "kind": "oracle",
                "sample": f"one oracle apply (2.13) of L1 on the {n}^3 M={M} field, FP64 numpy "
                          f"(pocketfft, single thread): {cpu_s:.1f} s"}
+        # accuracy of the benchmarked plan: L1 of the workload's initial field
+        # (as the plan sees it) against the FP64 oracle at sampled points
+        x_seen = c["u0"].astype(np.float32).astype(np.float64) if prec == "fp32" else c["u0"]
+        u_in = torch.from_numpy(c["u0"]).to(dev, tdt)
+        lu = plan.apply(V.VOFL_OP_S1, u_in).double().cpu().numpy().reshape(c["shape"])
+        rng = np.random.default_rng(np.random.SeedSequence(13049 + 3, spawn_key=(95,)))
+        pts = [tuple(n // 2 for n in c["shape"])] + [tuple(int(rng.integers(k)) for k in c["shape"]) for _ in range(5)]
+        t0 = time.perf_counter()
+        ref = O.mterm_apply_at(x_seen, 1.0 + gamma, c["lo"], c["hi"], M, pts)
+        acc_s = time.perf_counter() - t0
+        got = np.array([lu[j] for j in pts])
+        accuracy = {"max_abs_err_over_max_abs_out": float(np.max(np.abs(got - ref)) / np.max(np.abs(lu))),
+                    "points": len(pts), "operator": "L1 = (-Lap)^{1+gamma(x)} by (2.13)",
+                    "reference": f"FP64 oracle evaluated point by point ({acc_s:.1f} s)"}
         if not args.no_extras:
             workers = max(1, min(16, int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))))
             O.set_fft_workers(workers)
@@ -272,6 +287,7 @@ def main():
         "kernel_ms_per_step": {k: ms / args.steps for k, (ms, _) in ktimes.items()},
         "status": status,
         "fp64_path": fp64_cmp,
+        "accuracy": accuracy,
         "cpu_baseline": cpu,
         "cpu_oracle_multicore": cpu_mt,
     }
