@@ -50,14 +50,17 @@ __device__ __forceinline__ cpx<T> twmul(cpx<T> a, cpx<T> w) {
 __device__ __forceinline__ __amdgpu_buffer_rsrc_t make_rsrc(const void* base, unsigned bytes) {
     return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), (short)0, (int)bytes, 0x00020000);
 }
-template <typename T>
+// NT: non-temporal cache policy (data read once from a stream larger than
+// the caches).
+template <typename T, bool NT = false>
 __device__ __forceinline__ cpx<T> buffer_load_cpx(__amdgpu_buffer_rsrc_t r, unsigned off) {
+    constexpr int policy = NT ? 2 : 0;
     cpx<T> c;
     if constexpr (sizeof(T) == 4) {
-        auto v = __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, 0);
+        auto v = __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, policy);
         __builtin_memcpy(&c, &v, 8);
     } else {
-        auto v = __builtin_amdgcn_raw_buffer_load_b128(r, off, 0, 0);
+        auto v = __builtin_amdgcn_raw_buffer_load_b128(r, off, 0, policy);
         __builtin_memcpy(&c, &v, 16);
     }
     return c;

@@ -554,8 +554,10 @@ __device__ __forceinline__ int c2r_nslots(int mode, int M) {
 // (rows t + TP e for e < E/2 and the Nyquist row), and every thread reads
 // its rows min(k, N - k) from there; for lengths whose pencil positions
 // cannot be paired inside a wavefront.
+// NT: the slot loads use the non-temporal policy (launches whose slots are
+// larger than the last-level cache: they are read once and not kept).
 template <typename T, int N, int E, int W, int MODE, int WPE, int PD = 1, bool PAIRED = false,
-          bool STAGED = false>
+          bool STAGED = false, bool NT = false>
 __global__ __launch_bounds__(W*(N / E)) __attribute__((amdgpu_waves_per_eu(WPE)))
 void k_c2r0(C2RArgs<T> a) {
     static_assert(MODE >= 0 && MODE <= 3, "mode");
@@ -634,8 +636,8 @@ void k_c2r0(C2RArgs<T> a) {
         const auto r2 = make_rsrc(ibase + (long long)s2 * a.H, bytes);
 #pragma unroll
         for (int e = 0; e < NL; ++e) {
-            q1[e] = buffer_load_cpx<T>(r1, roff[e]);
-            q2[e] = buffer_load_cpx<T>(r2, roff[e]);
+            q1[e] = buffer_load_cpx<T, NT>(r1, roff[e]);
+            q2[e] = buffer_load_cpx<T, NT>(r2, roff[e]);
         }
     };
     auto shfl = [&](cpx<T> v) __attribute__((always_inline)) -> cpx<T> {

@@ -149,20 +149,30 @@ constexpr bool paired_ok() {
     return E % 2 == 0 && n / E >= 2 && W <= 32 && (64 / W) % 2 == 0 && ((n / E) * W) % 64 == 0;
 }
 
-template <typename T, int n, int E, int W, int WPE, int PD = 1, bool PAIRED = false, bool STAGED = false>
+template <typename T, int n, int E, int W, int WPE, int PD = 1, bool PAIRED = false, bool STAGED = false,
+          bool NT = false>
 hipError_t c2r0_mode(const C2RArgs<T>& a, int items, hipStream_t s) {
     const dim3 block(W * (n / E));
     const dim3 grid((a.inner + W - 1) / W, items);
     switch (a.mode) {
-        case C2R_APPLY: k_c2r0<T, n, E, W, C2R_APPLY, WPE, PD, PAIRED, STAGED><<<grid, block, 0, s>>>(a); break;
-        case C2R_KICK: k_c2r0<T, n, E, W, C2R_KICK, WPE, PD, PAIRED, STAGED><<<grid, block, 0, s>>>(a); break;
-        case C2R_EXPORT: k_c2r0<T, n, E, W, C2R_EXPORT, WPE, 1, PAIRED, STAGED><<<grid, block, 0, s>>>(a); break;
+        case C2R_APPLY: k_c2r0<T, n, E, W, C2R_APPLY, WPE, PD, PAIRED, STAGED, NT><<<grid, block, 0, s>>>(a); break;
+        case C2R_KICK: k_c2r0<T, n, E, W, C2R_KICK, WPE, PD, PAIRED, STAGED, NT><<<grid, block, 0, s>>>(a); break;
+        case C2R_EXPORT: k_c2r0<T, n, E, W, C2R_EXPORT, WPE, 1, PAIRED, STAGED, NT><<<grid, block, 0, s>>>(a); break;
         case C2R_KICK_GENERIC:
-            k_c2r0<T, n, E, W, C2R_KICK_GENERIC, WPE, PD, PAIRED, STAGED><<<grid, block, 0, s>>>(a);
+            k_c2r0<T, n, E, W, C2R_KICK_GENERIC, WPE, PD, PAIRED, STAGED, NT><<<grid, block, 0, s>>>(a);
             break;
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
+}
+
+// Bytes of term slots one k_c2r0 launch reads: above the 256 MB last-level
+// cache the paired default streams them with the non-temporal policy.
+template <typename T>
+bool c2r0_streams(const C2RArgs<T>& a, int items) {
+    const long long slots = a.mode == C2R_EXPORT ? 2 : a.mode == C2R_APPLY ? a.M + 1
+                          : a.mode == C2R_KICK ? 2LL * (a.M + 1) : a.M + 2;
+    return slots * a.H * (long long)sizeof(cpx<T>) * items > (256LL << 20);
 }
 
 template <typename T, int n, int E, int NW>
@@ -200,7 +210,9 @@ hipError_t Launch<T>::c2r0(int N, const C2RArgs<T>& a, int items, hipStream_t s,
         if constexpr (paired_ok<n, E, W2>() && W2 != W)                                  \
             if (variant == 13) return c2r0_mode<T, n, E, W2, 1, 1, true>(a, items, s);   \
         if constexpr (paired_ok<n, E, W>()) {                                           \
-            if (variant == 11) return c2r0_mode<T, n, E, W, 1, 1, true>(a, items, s);   \
+            if (variant == 11)                                                          \
+                return c2r0_streams(a, items) ? c2r0_mode<T, n, E, W, 1, 1, true, false, true>(a, items, s) \
+                                              : c2r0_mode<T, n, E, W, 1, 1, true>(a, items, s); \
             if constexpr (sizeof(T) == 4 && E <= 8)                                       \
                 if (variant == 12) return c2r0_mode<T, n, E, W, 1, 2, true>(a, items, s); \
         }                                                                               \
