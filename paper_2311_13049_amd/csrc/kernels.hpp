@@ -67,6 +67,23 @@ constexpr int line_group(int W, int B) {
     return (W * B >= 128) ? 1 : ((128 / (W * B)) > 8 ? 8 : 128 / (W * B));
 }
 
+// Non-temporal global load / store of one complex value (data streamed once
+// through a pass larger than the caches).
+template <typename T>
+__device__ __forceinline__ cpx<T> nt_load(const cpx<T>* p) {
+    typedef T v2 __attribute__((ext_vector_type(2)));
+    const v2 r = __builtin_nontemporal_load(reinterpret_cast<const v2*>(p));
+    return {r.x, r.y};
+}
+template <typename T>
+__device__ __forceinline__ void nt_store(cpx<T>* p, cpx<T> c) {
+    typedef T v2 __attribute__((ext_vector_type(2)));
+    v2 r;
+    r.x = c.x;
+    r.y = c.y;
+    __builtin_nontemporal_store(r, reinterpret_cast<v2*>(p));
+}
+
 // ---------------------------------------------------------------------------
 // pointwise helpers (FP64)
 // ---------------------------------------------------------------------------
@@ -375,7 +392,7 @@ struct MidArgs {
     const cpx<T>* tw;       // axis-1 twiddles
 };
 
-template <typename T, int N, int E, int W, int DIR>
+template <typename T, int N, int E, int W, int DIR, bool NT = false>
 __global__ __launch_bounds__(W*(N / E)) void k_mid(MidArgs<T> a) {
     constexpr int TP = N / E;
     __shared__ cpx<T> lds_raw[N * W];
@@ -396,12 +413,19 @@ __global__ __launch_bounds__(W*(N / E)) void k_mid(MidArgs<T> a) {
     const LdsColumn<T, W> lds{lds_raw + c};
     cpx<T> v[E];
 #pragma unroll
-    for (int e = 0; e < E; ++e) v[e] = base[(long long)(t + TP * e) * a.n2];
+    for (int e = 0; e < E; ++e) {
+        const cpx<T>* q = base + (long long)(t + TP * e) * a.n2;
+        v[e] = NT ? nt_load(q) : *q;
+    }
     if constexpr (num_stages(N, E) == 2) fft_pencil_once<T, N, E, DIR>(v, t, lds, tw_s);
     else fft_pencil<T, N, E, DIR>(v, t, lds, tw_s);
     if (active) {
 #pragma unroll
-        for (int e = 0; e < E; ++e) base[(long long)(t + TP * e) * a.n2] = v[e];
+        for (int e = 0; e < E; ++e) {
+            cpx<T>* q = base + (long long)(t + TP * e) * a.n2;
+            if constexpr (NT) nt_store(q, v[e]);
+            else *q = v[e];
+        }
     }
 }
 

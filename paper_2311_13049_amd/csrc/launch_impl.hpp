@@ -78,6 +78,21 @@ hipError_t Launch<T>::contig(int N, const ContigArgs<T, TI>& a, int items, hipSt
     }
 }
 
+// One middle-axis launch of tile width W; nt: the launch moves more than
+// the 256 MB last-level cache holds, so slots are loaded and stored with the
+// non-temporal policy.
+template <typename T, int n, int E, int W>
+void mid_launch(int dir, bool nt, dim3 grid, const MidArgs<T>& a, hipStream_t s) {
+    const dim3 block(W * (n / E));
+    if (nt) {
+        if (dir < 0) k_mid<T, n, E, W, -1, true><<<grid, block, 0, s>>>(a);
+        else k_mid<T, n, E, W, +1, true><<<grid, block, 0, s>>>(a);
+    } else {
+        if (dir < 0) k_mid<T, n, E, W, -1><<<grid, block, 0, s>>>(a);
+        else k_mid<T, n, E, W, +1><<<grid, block, 0, s>>>(a);
+    }
+}
+
 // variants: 0 -> W = tile_width columns; 1 -> 2W columns when the FFT
 // buffer stays within 66 KB of LDS
 template <typename T>
@@ -92,16 +107,11 @@ hipError_t Launch<T>::mid(int N, int dir, const MidArgs<T>& a, int planes, int i
                             4 * W * (n / E) <= 1024) ? 4 * W : W2;                      \
         const int w = (variant == 2) ? W4 : (variant == 1) ? W2 : W;                   \
         dim3 grid(planes * ((a.n2 + w - 1) / w), items * a.nf);                         \
-        if (variant == 2 && W4 != W2) {                                                 \
-            if (dir < 0) k_mid<T, n, E, W4, -1><<<grid, dim3(W4 * (n / E)), 0, s>>>(a); \
-            else k_mid<T, n, E, W4, +1><<<grid, dim3(W4 * (n / E)), 0, s>>>(a);        \
-        } else if ((variant == 1 || variant == 2) && W2 != W) {                         \
-            if (dir < 0) k_mid<T, n, E, W2, -1><<<grid, dim3(W2 * (n / E)), 0, s>>>(a); \
-            else k_mid<T, n, E, W2, +1><<<grid, dim3(W2 * (n / E)), 0, s>>>(a);        \
-        } else {                                                                        \
-            if (dir < 0) k_mid<T, n, E, W, -1><<<grid, dim3(W * (n / E)), 0, s>>>(a);   \
-            else k_mid<T, n, E, W, +1><<<grid, dim3(W * (n / E)), 0, s>>>(a);          \
-        }                                                                               \
+        const bool nt = (long long)planes * n * a.n2 * items * a.nf * (long long)sizeof(cpx<T>) > \
+                        (256LL << 20);                                                  \
+        if (variant == 2 && W4 != W2) mid_launch<T, n, E, W4>(dir, nt, grid, a, s);     \
+        else if ((variant == 1 || variant == 2) && W2 != W) mid_launch<T, n, E, W2>(dir, nt, grid, a, s); \
+        else mid_launch<T, n, E, W>(dir, nt, grid, a, s);                               \
         return hipGetLastError();                                                       \
     }
         VOFL_MULTI_SIZES(C_)
