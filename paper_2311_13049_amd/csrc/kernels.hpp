@@ -190,7 +190,9 @@ struct ContigArgs {
 
 // Input spectra (forward transforms of caller data, and the FP64 staging)
 // are transformed in precision TI; the term spectra in precision T.
-template <typename T, typename TI, int N, int E, int P>
+// NT: the step's term slots are stored with the non-temporal policy (launches
+// whose slots exceed the last-level cache).
+template <typename T, typename TI, int N, int E, int P, bool NT = false>
 __global__ __launch_bounds__(P*(N / E)) void k_contig(ContigArgs<T, TI> a) {
     constexpr int TP = N / E;
     constexpr int FPI = LdsPencil<TI>::footprint(N);
@@ -345,7 +347,10 @@ __global__ __launch_bounds__(P*(N / E)) void k_contig(ContigArgs<T, TI> a) {
             if (active) {
                 cpx<T>* d = dst0 + (long long)(2 * m) * a.H;
 #pragma unroll
-                for (int e = 0; e < E; ++e) d[t + TP * e] = x[e];
+                for (int e = 0; e < E; ++e) {
+                    if constexpr (NT) nt_store(d + t + TP * e, x[e]);
+                    else d[t + TP * e] = x[e];
+                }
             }
 #pragma unroll
             for (int e = 0; e < E; ++e) x[e] = from_d<T>(vh[e]);
@@ -353,7 +358,10 @@ __global__ __launch_bounds__(P*(N / E)) void k_contig(ContigArgs<T, TI> a) {
             if (active) {
                 cpx<T>* d = dst0 + (long long)(2 * m + 1) * a.H;
 #pragma unroll
-                for (int e = 0; e < E; ++e) d[t + TP * e] = x[e];
+                for (int e = 0; e < E; ++e) {
+                    if constexpr (NT) nt_store(d + t + TP * e, x[e]);
+                    else d[t + TP * e] = x[e];
+                }
             }
             const double inv = 1.0 / double(m + 1);
 #pragma unroll

@@ -61,6 +61,14 @@ int Launch<T>::c2r_w(int N) {
     }
 }
 
+// Term slots a step's last-axis launch writes: above the 256 MB last-level
+// cache they are stored with the non-temporal policy.
+template <typename T, typename TI>
+bool contig_streams(const ContigArgs<T, TI>& a, int items) {
+    if (a.emit_kind != EMIT_STEP) return false;
+    return 2LL * (a.M + 1) * a.H * (long long)sizeof(cpx<T>) * items > (256LL << 20);
+}
+
 template <typename T>
 template <typename TI>
 hipError_t Launch<T>::contig(int N, const ContigArgs<T, TI>& a, int items, hipStream_t s) {
@@ -69,7 +77,8 @@ hipError_t Launch<T>::contig(int N, const ContigArgs<T, TI>& a, int items, hipSt
     case n: {                                                                           \
         constexpr int E = e_contig(n), P = p_contig(n);                                 \
         dim3 grid((a.npencils + P - 1) / P, items);                                     \
-        k_contig<T, TI, n, E, P><<<grid, dim3(P * (n / E)), 0, s>>>(a);                 \
+        if (contig_streams(a, items)) k_contig<T, TI, n, E, P, true><<<grid, dim3(P * (n / E)), 0, s>>>(a); \
+        else k_contig<T, TI, n, E, P><<<grid, dim3(P * (n / E)), 0, s>>>(a);            \
         return hipGetLastError();                                                       \
     }
         VOFL_MULTI_SIZES(C_)
