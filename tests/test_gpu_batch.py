@@ -15,7 +15,7 @@ import numpy as np
 import pytest
 
 import oracle as O
-from gpu_helpers import TOL_FP32, as_seen, dev, host, rel_l2, require_gpu, say
+from gpu_helpers import TOL_FP32, as_seen, dev, host, parity_err, require_gpu, say
 from workloads import c4_inputs
 
 pytestmark = pytest.mark.gpu
@@ -96,12 +96,12 @@ def test_c4_batch_sampled_shots_vs_oracle(c4):
         shots = small if grp == "512" else big
         say(f"  oracle shot {grp}^2 #{idx}")
         ru, rv = _oracle(c4, shots[idx], ORACLE_STEPS)
-        eu = rel_l2(hu[idx], ru)
-        say(f"    rel L2 u {eu:.3e}")
+        eu = parity_err(hu[idx], ru)
+        say(f"    parity err u {eu:.3e}")
         assert eu <= TOL_FP32
         if hv is not None:
-            ev = rel_l2(hv[idx], rv)
-            say(f"    rel L2 v {ev:.3e}")
+            ev = parity_err(hv[idx], rv)
+            say(f"    parity err v {ev:.3e}")
             assert ev <= TOL_FP32
 
 
@@ -209,8 +209,8 @@ def test_autotuned_plans_pick_listed_variants_and_stay_accurate(c4, tmp_path):
             p.step(u, v, 10)
             torch.cuda.synchronize()
             ru, _ = _oracle(c4, shots[1], 10)
-            e = rel_l2(host(u).reshape((4,) + shots[0]["shape"])[1], ru)
-            say(f"  variant {info['c2r_variant']}: rel L2 {e:.3e}")
+            e = parity_err(host(u).reshape((4,) + shots[0]["shape"])[1], ru)
+            say(f"  variant {info['c2r_variant']}: parity err {e:.3e}")
             assert e <= TOL_FP32
             p.close()
             q.close()

@@ -8,7 +8,7 @@ import numpy as np
 import pytest
 
 import oracle as O
-from gpu_helpers import as_seen, dev, host, rel_l2, require_gpu, say, tol
+from gpu_helpers import as_seen, dev, host, parity_err, require_gpu, say, tol
 from workloads import gaussian_pulse, grid_1d, mesh, paper_s1
 
 pytestmark = pytest.mark.gpu
@@ -39,8 +39,8 @@ def test_1d_example_41_vs_oracle(precision):
     p = _plan((J,), lo, hi, precision, s=s, kappa=1.0, lam=1.0, M=M, dt=dt)
     up, u, its = _run(p, phi, psi, precision, steps, 1e-14 if precision == "fp64" else 1e-6)
     rp, ru = O.cnfp_generic(as_seen(phi, precision), psi, s, 1.0, lo, hi, M, dt, steps, f=lambda w: w ** 3)
-    eu, ep = rel_l2(host(u), ru), rel_l2(host(up), rp)
-    say(f"  BiCGSTAB iterations {its}; rel L2 u {eu:.2e} u_prev {ep:.2e}")
+    eu, ep = parity_err(host(u), ru), parity_err(host(up), rp)
+    say(f"  BiCGSTAB iterations {its}; parity err u {eu:.2e} u_prev {ep:.2e}")
     assert eu <= tol(precision) and ep <= tol(precision)
 
 
@@ -81,8 +81,8 @@ def test_nd_vs_oracle(shape, precision):
     up, u, its = _run(p, phi, psi, precision, 8, 1e-13 if precision == "fp64" else 1e-6)
     rp, ru = O.cnfp_generic(as_seen(phi, precision), as_seen(psi, precision), s, 0.7, lo, hi, 8, 5e-3, 8,
                             f=lambda w: 0.5 * w ** 3)
-    eu, ep = rel_l2(host(u), ru), rel_l2(host(up), rp)
-    say(f"  BiCGSTAB iterations {its}; rel L2 u {eu:.2e} u_prev {ep:.2e}")
+    eu, ep = parity_err(host(u), ru), parity_err(host(up), rp)
+    say(f"  BiCGSTAB iterations {its}; parity err u {eu:.2e} u_prev {ep:.2e}")
     assert eu <= tol(precision) and ep <= tol(precision)
 
 
@@ -124,7 +124,7 @@ def test_batched_solves_vs_oracle(shape, per_solve, precision):
     for b in range(3):
         rp, ru = O.cnfp_generic(as_seen(phis[b], precision), np.zeros(shape), ss[b], 0.8, lo, hi, M, dt, steps,
                                 f=lambda w: 0.4 * w ** 3)
-        eu, ep = rel_l2(hu[b], ru), rel_l2(hp[b], rp)
-        say(f"  solve {b}: rel L2 u {eu:.2e} u_prev {ep:.2e}")
+        eu, ep = parity_err(hu[b], ru), parity_err(hp[b], rp)
+        say(f"  solve {b}: parity err u {eu:.2e} u_prev {ep:.2e}")
         assert eu <= tol(precision) and ep <= tol(precision)
     say(f"  BiCGSTAB iterations (all solves) {its}")

@@ -9,7 +9,7 @@ import numpy as np
 import pytest
 
 import oracle as O
-from gpu_helpers import as_seen, dev, host, rel_l2, require_gpu, say, tol
+from gpu_helpers import as_seen, dev, host, parity_err, require_gpu, say, tol
 from workloads import gaussian_pulse, grid_1d, mesh, paper_s1
 
 pytestmark = pytest.mark.gpu
@@ -41,8 +41,8 @@ def test_1d_example_41_vs_oracle(precision):
     p.lffp_step(up, u, 63)
     assert p.sync_status() == 0
     rp, ru = O.lffp_generic(as_seen(phi, precision), psi, s, 1.0, lo, hi, M, dt, 64, f=_cube)
-    eu, ep = rel_l2(host(u), ru), rel_l2(host(up), rp)
-    say(f"  rel L2 u {eu:.2e} u_prev {ep:.2e}")
+    eu, ep = parity_err(host(u), ru), parity_err(host(up), rp)
+    say(f"  parity err u {eu:.2e} u_prev {ep:.2e}")
     assert eu <= tol(precision) and ep <= tol(precision)
 
 
@@ -108,8 +108,8 @@ def test_nd_vs_oracle(case, precision):
     assert p.sync_status() == 0
     rp, ru = O.lffp_generic(as_seen(phi, precision), as_seen(psi, precision), s, 0.7, lo, hi, M, dt,
                             steps, f=lambda w: 0.5 * w ** 3)
-    eu, ep = rel_l2(host(u), ru), rel_l2(host(up), rp)
-    say(f"  rel L2 u {eu:.2e} u_prev {ep:.2e}")
+    eu, ep = parity_err(host(u), ru), parity_err(host(up), rp)
+    say(f"  parity err u {eu:.2e} u_prev {ep:.2e}")
     assert eu <= tol(precision) and ep <= tol(precision)
 
 
@@ -141,4 +141,4 @@ def test_batched_solves_with_own_orders():
     hu = host(u).reshape((2,) + shape)
     for i in range(2):
         _, ru = O.lffp_generic(phis[i], np.zeros(shape), ss[i], 1.0, lo, hi, 7, 1e-3, 10, f=_cube)
-        assert rel_l2(hu[i], ru) <= 1e-12
+        assert parity_err(hu[i], ru) <= 1e-12

@@ -10,7 +10,7 @@ import numpy as np
 import pytest
 
 import oracle as O
-from gpu_helpers import as_seen, dev, host, rel_l2, require_gpu, say, tol
+from gpu_helpers import as_seen, dev, host, parity_err, require_gpu, say, tol
 from workloads import c1_inputs, ex3_inputs, gaussian_pulse, grf_Q, grid_1d, mesh, rng_for, ricker
 
 pytestmark = pytest.mark.gpu
@@ -48,8 +48,8 @@ def test_1d_c1_vs_oracle(precision):
     up, u = _run_gpu(p, c["u0"], psi, precision, 100)
     rp, ru = O.lffp_seismic(as_seen(c["u0"], precision), as_seen(psi, precision), c["gamma"], 1.3, 0.7,
                             c["lo"], c["hi"], c["M"], c["dt"], 100)
-    eu, ep = rel_l2(u, ru), rel_l2(up, rp)
-    say(f"  rel L2 u {eu:.2e} u_prev {ep:.2e}")
+    eu, ep = parity_err(u, ru), parity_err(up, rp)
+    say(f"  parity err u {eu:.2e} u_prev {ep:.2e}")
     assert eu <= tol(precision) and ep <= tol(precision)
 
 
@@ -68,8 +68,8 @@ def test_2d_layered_medium_vs_oracle(precision, shape):
     up, u = _run_gpu(p, phi, psi, precision, steps)
     rp, ru = O.lffp_seismic(as_seen(phi, precision), as_seen(psi, precision), gamma, c0, 1.0, lo, hi, M, dt,
                             steps)
-    eu, ep = rel_l2(u, ru), rel_l2(up, rp)
-    say(f"  rel L2 u {eu:.2e} u_prev {ep:.2e}")
+    eu, ep = parity_err(u, ru), parity_err(up, rp)
+    say(f"  parity err u {eu:.2e} u_prev {ep:.2e}")
     assert eu <= tol(precision) and ep <= tol(precision)
 
 
@@ -92,8 +92,8 @@ def test_3d_batch_own_coefficients_vs_oracle(precision):
     for b in range(2):
         rp, ru = O.lffp_seismic(as_seen(u0s[b], precision), np.zeros(shape), O.gamma_from_Q(Qs[b]), c0s[b], 1.5,
                                 lo, hi, M, dt, steps)
-        eu, ep = rel_l2(u[b], ru), rel_l2(up[b], rp)
-        say(f"  solve {b}: rel L2 u {eu:.2e} u_prev {ep:.2e}")
+        eu, ep = parity_err(u[b], ru), parity_err(up[b], rp)
+        say(f"  solve {b}: parity err u {eu:.2e} u_prev {ep:.2e}")
         assert eu <= tol(precision) and ep <= tol(precision)
 
 
@@ -154,8 +154,8 @@ def test_example3_full_grid_vs_oracle(precision):
                                 ex["lo"], ex["hi"], ex["M"], ex["dt"], steps)
     finally:
         O.set_fft_workers(0)
-    eu = rel_l2(u.reshape(ex["shape"]), ru)
-    say(f"  rel L2 u {eu:.2e}")
+    eu = parity_err(u.reshape(ex["shape"]), ru)
+    say(f"  parity err u {eu:.2e}")
     assert eu <= tol(precision)
 
 
@@ -189,8 +189,8 @@ def test_1d_batch_own_gamma_and_c0_vs_oracle(precision):
     for b in range(3):
         _, ru = O.lffp_seismic(as_seen(phis[b], precision), np.zeros(n), gammas[b], c0s[b], 1.2, lo, hi, M, dt,
                                steps)
-        e = rel_l2(u[b], ru)
-        say(f"  solve {b}: rel L2 u {e:.2e}")
+        e = parity_err(u[b], ru)
+        say(f"  solve {b}: parity err u {e:.2e}")
         assert e <= tol(precision)
 
 
@@ -204,6 +204,6 @@ def test_2d_radix3_grid_vs_oracle():
     p = _plan(shape, lo, hi, "fp64", gamma=gamma, c0_field=c0, M=M, dt=dt)
     up, u = _run_gpu(p, phi, np.zeros(shape), "fp64", steps)
     _, ru = O.lffp_seismic(phi, np.zeros(shape), gamma, c0, 1.0, lo, hi, M, dt, steps)
-    e = rel_l2(u.reshape(shape), ru)
-    say(f"  rel L2 u {e:.2e}")
+    e = parity_err(u.reshape(shape), ru)
+    say(f"  parity err u {e:.2e}")
     assert e <= tol("fp64")

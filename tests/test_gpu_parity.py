@@ -6,7 +6,7 @@ import numpy as np
 import pytest
 
 import oracle as O
-from gpu_helpers import as_seen, dev, host, rel_l2, require_gpu, say, tol
+from gpu_helpers import as_seen, dev, host, parity_err, require_gpu, say, tol
 from workloads import c1_inputs, gaussian_pulse, grf_Q, grid_1d, mesh, paper_s1, rng_for
 
 pytestmark = pytest.mark.gpu
@@ -34,8 +34,8 @@ def test_apply_1d_c1_vs_dense_and_mterm(precision):
         s = O.seismic_op_order(c["gamma"], op)
         ref_m = O.mterm_apply(u_in, s, c["lo"], c["hi"], c["M"])
         ref_d = O.dense_apply(u_in, s, c["lo"], c["hi"])
-        assert rel_l2(out, ref_m) <= tol(precision), (op, rel_l2(out, ref_m))
-        assert rel_l2(out, ref_d) <= tol(precision) + 1e-13, (op, rel_l2(out, ref_d))
+        assert parity_err(out, ref_m) <= tol(precision), (op, parity_err(out, ref_m))
+        assert parity_err(out, ref_d) <= tol(precision) + 1e-13, (op, parity_err(out, ref_d))
 
 
 CASES_ND = [
@@ -73,7 +73,7 @@ def test_apply_nd_vs_mterm(case, precision, M):
     for op in (1, 2):
         out = host(p.apply(op, u))
         ref = O.mterm_apply(as_seen(u0, precision), O.seismic_op_order(gamma, op), lo, hi, M)
-        assert rel_l2(out, ref) <= tol(precision), (op, rel_l2(out, ref))
+        assert parity_err(out, ref) <= tol(precision), (op, parity_err(out, ref))
 
 
 def test_apply_batch_of_fields_fp64():
@@ -86,7 +86,7 @@ def test_apply_batch_of_fields_fp64():
     out = host(p.apply(2, dev(U, "fp64"))).reshape(U.shape)
     for f in range(3):
         ref = O.mterm_apply(U[f], O.seismic_op_order(gamma, 2), lo, hi, 6)
-        assert rel_l2(out[f], ref) <= 1e-12
+        assert parity_err(out[f], ref) <= 1e-12
 
 
 def test_apply_small_grid_vs_dense():
@@ -96,7 +96,7 @@ def test_apply_small_grid_vs_dense():
     p = _plan(shape, lo, hi, "fp64", Q=Q, M=24, dt=1e-3)
     out = host(p.apply(1, dev(u0, "fp64")))
     ref = O.dense_apply(u0, O.seismic_op_order(gamma, 1), lo, hi)
-    assert rel_l2(out, ref) <= 1e-12
+    assert parity_err(out, ref) <= 1e-12
 
 
 def test_apply_constant_order_single_mode_exact():
@@ -111,7 +111,7 @@ def test_apply_constant_order_single_mode_exact():
         p = _plan(shape, lo, hi, precision, gamma=np.full(shape, g), M=3, dt=1e-3)
         out = host(p.apply(1, dev(u0, precision)))
         expect = (mu[0] ** 2 + mu[1] ** 2) ** (1 + g) * as_seen(u0, precision)
-        assert rel_l2(out, expect) <= tol(precision), k
+        assert parity_err(out, expect) <= tol(precision), k
 
 
 # --------------------------------------------------------------------------
@@ -129,11 +129,11 @@ def test_apply_and_step_1d_mixed_radix(n):
     u0 = np.exp(-x * x)
     p = _plan((n,), lo, hi, "fp64", gamma=gamma, M=10, dt=2e-3)
     out = host(p.apply(1, dev(u0, "fp64")))
-    assert rel_l2(out, O.mterm_apply(u0, 1.0 + gamma, lo, hi, 10)) <= 1e-12
+    assert parity_err(out, O.mterm_apply(u0, 1.0 + gamma, lo, hi, 10)) <= 1e-12
     u, v = dev(u0, "fp64"), dev(np.zeros(n), "fp64")
     p.step(u, v, 20)
     ru, _ = O.tsfp2_seismic(u0, np.zeros(n), gamma, 1.0, 1.0, lo, hi, 10, 2e-3, 20)
-    assert rel_l2(host(u), ru) <= 1e-12
+    assert parity_err(host(u), ru) <= 1e-12
 
 
 @pytest.mark.parametrize("precision", ["fp64", "fp32"])
@@ -146,8 +146,8 @@ def test_step_1d_c1(precision):
     assert p.sync_status() == 0
     ru, rv = O.tsfp2_seismic(as_seen(c["u0"], precision), c["v0"], c["gamma"], c["c0"], c["omega0"],
                              c["lo"], c["hi"], c["M"], c["dt"], c["steps"])
-    eu, ev = rel_l2(host(u), ru), rel_l2(host(v), rv)
-    say(f"  rel L2 u {eu:.2e} v {ev:.2e}")
+    eu, ev = parity_err(host(u), ru), parity_err(host(v), rv)
+    say(f"  parity err u {eu:.2e} v {ev:.2e}")
     assert eu <= tol(precision), eu
     assert ev <= tol(precision), ev
 
@@ -180,8 +180,8 @@ def test_step_nd_vs_oracle(case, precision):
     assert p.sync_status() == 0
     ru, rv = O.tsfp2_seismic(as_seen(u0, precision), as_seen(v0, precision), gamma, 1.2, 2.0, lo, hi,
                              M, dt, steps)
-    eu, ev = rel_l2(host(u), ru), rel_l2(host(v), rv)
-    say(f"  rel L2 u {eu:.2e} v {ev:.2e}")
+    eu, ev = parity_err(host(u), ru), parity_err(host(v), rv)
+    say(f"  parity err u {eu:.2e} v {ev:.2e}")
     assert eu <= tol(precision), eu
     assert ev <= tol(precision), ev
 
@@ -206,7 +206,7 @@ def test_step_split_calls_equal_one_call():
     u2, v2 = dev(u0, "fp64"), dev(np.zeros(shape), "fp64")
     p.step(u2, v2, 4)
     p.step(u2, v2, 6)
-    assert rel_l2(host(u2), host(u1)) <= 1e-13
+    assert parity_err(host(u2), host(u1)) <= 1e-13
 
 
 @pytest.mark.parametrize("ndim", [1, 2])
@@ -228,7 +228,7 @@ def test_step_batch_per_solve_coefficients(ndim):
     hu = host(u).reshape((3,) + shape)
     for i in range(3):
         ru, _ = O.tsfp2_seismic(us[i], np.zeros(shape), gs[i], 1.0, 1.0, lo, hi, 5, 2e-3, 7)
-        assert rel_l2(hu[i], ru) <= 1e-12
+        assert parity_err(hu[i], ru) <= 1e-12
 
 
 # --------------------------------------------------------------------------
@@ -247,7 +247,7 @@ def test_generic_1d_example_41(precision):
     u, v = dev(u0, precision), dev(v0, precision)
     p.step(u, v, steps)
     ru, rv = O.tsfp2_generic(as_seen(u0, precision), v0, s, 1.0, lo, hi, M, dt, steps, f=lambda w: w ** 3)
-    assert rel_l2(host(u), ru) <= tol(precision)
+    assert parity_err(host(u), ru) <= tol(precision)
 
 
 @pytest.mark.parametrize("shape", [(32, 64), (16, 16, 16)])
@@ -261,7 +261,7 @@ def test_generic_nd(shape):
     u, v = dev(u0, "fp64"), dev(np.zeros(shape), "fp64")
     p.step(u, v, 9)
     ru, _ = O.tsfp2_generic(u0, np.zeros(shape), s, 0.7, lo, hi, 10, 1e-3, 9, f=lambda w: 0.5 * w ** 3)
-    assert rel_l2(host(u), ru) <= 1e-12
+    assert parity_err(host(u), ru) <= 1e-12
 
 
 def test_unstable_flag_table4_entry():
@@ -307,13 +307,13 @@ def test_axis0_variants_apply_and_step(case, precision, variant):
     u_in = as_seen(u0, precision)
     out = host(p.apply(1, dev(u0, precision))).reshape(shape)
     ref = O.mterm_apply(u_in, 1.0 + gamma, lo, hi, 6)
-    assert rel_l2(out, ref) <= tol(precision), rel_l2(out, ref)
+    assert parity_err(out, ref) <= tol(precision), parity_err(out, ref)
     u, v = dev(u0, precision), dev(np.zeros(shape), precision)
     p.step(u, v, 4)
     assert p.sync_status() == 0
     ru, rv = O.tsfp2_seismic(u_in, np.zeros(shape), gamma, 1.0, 1.0, lo, hi, 6, 2e-3, 4)
-    eu, ev = rel_l2(host(u), ru), rel_l2(host(v), rv)
-    say(f"  rel L2 u {eu:.2e} v {ev:.2e}")
+    eu, ev = parity_err(host(u), ru), parity_err(host(v), rv)
+    say(f"  parity err u {eu:.2e} v {ev:.2e}")
     assert eu <= tol(precision), eu
     assert ev <= tol(precision), ev
 
@@ -337,12 +337,12 @@ def test_mid_variants_apply_and_step(precision, mid_variant):
     u_in = as_seen(u0, precision)
     out = host(p.apply(2, dev(u0, precision))).reshape(shape)
     ref = O.mterm_apply(u_in, 0.5 + gamma, lo, hi, 4)
-    assert rel_l2(out, ref) <= tol(precision), rel_l2(out, ref)
+    assert parity_err(out, ref) <= tol(precision), parity_err(out, ref)
     u, v = dev(u0, precision), dev(np.zeros(shape), precision)
     p.step(u, v, 3)
     assert p.sync_status() == 0
     ru, rv = O.tsfp2_seismic(u_in, np.zeros(shape), gamma, 1.0, 1.0, lo, hi, 4, 2e-3, 3)
-    eu, ev = rel_l2(host(u), ru), rel_l2(host(v), rv)
-    say(f"  rel L2 u {eu:.2e} v {ev:.2e}")
+    eu, ev = parity_err(host(u), ru), parity_err(host(v), rv)
+    say(f"  parity err u {eu:.2e} v {ev:.2e}")
     assert eu <= tol(precision), eu
     assert ev <= tol(precision), ev

@@ -12,7 +12,7 @@ import numpy as np
 import pytest
 
 import oracle as O
-from gpu_helpers import TOL_FP32, TOL_FP64, as_seen, rel_l2, require_gpu, say
+from gpu_helpers import TOL_FP32, TOL_FP64, as_seen, parity_err, require_gpu, say
 from workloads import c5_requests
 
 pytestmark = pytest.mark.gpu
@@ -48,14 +48,14 @@ def test_mix_equals_alone_and_oracle():
         a, b, c = mix[r.index], alone[r.index], whole[r.index]
         assert a.status == "ok" and b.status == "ok" and c.status == "ok"
         assert np.array_equal(a.u, b.u) and np.array_equal(a.v, b.v), f"request {r.index}"
-        assert rel_l2(a.u, c.u) <= (TOL_FP32 if r.precision == "fp32" else TOL_FP64)
+        assert parity_err(a.u, c.u) <= (TOL_FP32 if r.precision == "fp32" else TOL_FP64)
     for prec in ("fp64", "fp32"):
         r = next(q for q in reqs if q.precision == prec)
         say(f"  oracle check request {r.index} {r.shape} M={r.M} steps={r.steps} {prec}")
         ru, rv = O.tsfp2_seismic(as_seen(r.u0, prec), np.zeros(r.shape), O.gamma_from_Q(r.Q),
                                  r.c0, r.omega0, r.lo, r.hi, r.M, r.dt, r.steps)
-        e = rel_l2(mix[r.index].u, ru)
-        say(f"    rel L2 {e:.3e}")
+        e = parity_err(mix[r.index].u, ru)
+        say(f"    parity err {e:.3e}")
         assert e <= (TOL_FP32 if prec == "fp32" else TOL_FP64)
 
 

@@ -5,7 +5,7 @@ import numpy as np
 import pytest
 
 import oracle as O
-from gpu_helpers import as_seen, dev, host, rel_l2, require_gpu, say, tol
+from gpu_helpers import as_seen, dev, host, parity_err, require_gpu, say, tol
 from workloads import gaussian_pulse, grid_1d, mesh, paper_s1
 
 pytestmark = pytest.mark.gpu
@@ -33,8 +33,8 @@ def test_1d_example_41(precision):
     assert p.sync_status() == 0
     ru, rv = O.tsfp4_generic(as_seen(u0, precision), as_seen(v0, precision), s, 1.0, lo, hi, M, dt, steps,
                              f=lambda w: w ** 3)
-    eu, ev = rel_l2(host(u), ru), rel_l2(host(v), rv)
-    say(f"  rel L2 u {eu:.2e} v {ev:.2e}")
+    eu, ev = parity_err(host(u), ru), parity_err(host(v), rv)
+    say(f"  parity err u {eu:.2e} v {ev:.2e}")
     assert eu <= tol(precision) and ev <= tol(precision)
 
 
@@ -54,8 +54,8 @@ def test_nd(shape, precision):
     assert p.sync_status() == 0
     ru, rv = O.tsfp4_generic(as_seen(u0, precision), as_seen(v0, precision), s, 0.7, lo, hi, 10, 2e-3, 7,
                              f=lambda w: 0.5 * w ** 3)
-    eu, ev = rel_l2(host(u), ru), rel_l2(host(v), rv)
-    say(f"  rel L2 u {eu:.2e} v {ev:.2e}")
+    eu, ev = parity_err(host(u), ru), parity_err(host(v), rv)
+    say(f"  parity err u {eu:.2e} v {ev:.2e}")
     assert eu <= tol(precision) and ev <= tol(precision)
 
 
@@ -71,7 +71,7 @@ def test_batched_per_solve_orders():
     hu = host(u).reshape((2,) + shape)
     for i in range(2):
         ru, _ = O.tsfp4_generic(us[i], np.zeros(shape), ss[i], 1.0, lo, hi, 7, 1e-3, 5, f=lambda w: w ** 3)
-        assert rel_l2(hu[i], ru) <= 1e-12
+        assert parity_err(hu[i], ru) <= 1e-12
 
 
 def test_seismic_model_rejects_order_4():

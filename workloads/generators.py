@@ -32,7 +32,7 @@ __all__ = [
     "BASE_SEED", "rng_for", "grid_1d", "mesh", "gaussian_pulse", "grf_Q",
     "two_layer_Q", "c1_inputs", "c2_inputs", "c3_inputs", "c4_inputs",
     "c5_requests", "c5_request_inputs", "paper_s1", "paper_s2", "paper_ex1_initial",
-    "ricker", "ex3_inputs",
+    "ricker", "ex3_inputs", "probe_field",
 ]
 
 BASE_SEED = 13049
@@ -220,3 +220,10 @@ def ex3_inputs(n: int = 1000, case: int = 0):
     phi = ricker(shape, lo, hi, (1.0, 0.85), 25.0)
     return dict(shape=shape, lo=lo, hi=hi, gamma=gamma, c0=c0, omega0=1.0, M=8, dt=1e-4,
                 phi=phi, psi=np.zeros(shape), a1=a1, a2=a2)
+
+
+def probe_field(shape, index: int) -> np.ndarray:
+    """Seeded standard-normal field number ``index``: test vectors onto which
+    stored results are projected (the projections of an error field estimate
+    its L2 norm; nothing of the method is computed here)."""
+    return rng_for(90, int(index)).standard_normal(tuple(int(n) for n in shape))
