@@ -120,7 +120,9 @@ int vofl_plan(const vofl_desc* desc, void* stream, vofl_plan_t* out);
  * no device access). Returns VOFL_OK and writes *bytes, or an error code. */
 int vofl_plan_footprint(const vofl_desc* desc, size_t* bytes);
 
-/* Apply the M-term operator (2.13) to nfields real fields:
+/* Apply the M-term operator (2.13) to nfields real fields (the proposal of
+ * one field per call is widened to nfields so that the L1 u / L2 v pair of a
+ * step, or a batch of fields, shares the launches):
  * out_f = (L_op u_f) for f < nfields, with op VOFL_OP_S1 or VOFL_OP_S2.
  * u, out: device, nfields * N values each, plan precision, out != u,
  * no overlap. Asynchronous on stream. 1 <= nfields <= max_batch; with
@@ -130,11 +132,50 @@ int vofl_apply(vofl_plan_t plan, int op, const void* u, void* out, int nfields,
 
 /* Advance (u, v = u_t) by nsteps TSFP2 steps (eqs. (3.13)-(3.14); for (1.1)
  * the exact part is the damped oscillator of the mean orders and the kick
- * carries the variable-order remainder). u, v: device, N values each,
- * overwritten in place. nsteps >= 0. Asynchronous on stream; a non-finite
- * value sets the plan's device flag, reported as VOFL_ERR_UNSTABLE by the
- * next vofl_sync_status (and by later vofl_step calls after a sync). */
+ * carries the variable-order remainder). u, v: device, batch * N values
+ * each, overwritten in place. nsteps >= 0. Asynchronous on stream; a
+ * non-finite value sets the plan's device flag, reported as
+ * VOFL_ERR_UNSTABLE by the next vofl_sync_status (and by later vofl_step
+ * calls after a sync).
+ * Order in dt: second for the generic model (1.5) (the kick is exact in
+ * time there), and for (1.1) when gamma is constant (the remainder is then
+ * zero and the step is exact in time). For (1.1) with a non-constant gamma
+ * the kick holds v at its half-step value inside the variable damping term
+ * -(B(x) L2 - beta0 |mu|^{2(1/2+gbar)}) v, so the split is first order in
+ * dt; for the same reason order = 4 is refused for the seismic model.
+ * Every call on a plan (vofl_apply, vofl_step*, vofl_lffp_*, vofl_cnfp_step)
+ * uses the plan's work slots and spectral blocks: calls on one plan must be
+ * issued on one stream, or ordered with events; two streams using one plan
+ * at once race. */
 int vofl_step(vofl_plan_t plan, void* u, void* v, int nsteps, void* stream);
+
+/* Resumable TSFP2 run (eqs. (3.13)-(3.14)) with the spectral state kept in
+ * the plan between calls, for callers that advance a solve in chunks
+ * (request servers, graph replays) or read the wavefield while stepping.
+ *
+ * vofl_step_begin: imports (u, v) (device, batch * N values each, plan
+ * precision; read only) into the plan's FP64 spectral state at t_0.
+ * vofl_step_advance: nsteps >= 0 TSFP2 steps of the run. It touches no
+ * caller memory, so its launches depend on nsteps alone; use_graph != 0
+ * replays a HIP graph captured once per nsteps (up to 8 kept per plan; no
+ * device memory allocated by the library). The state is carried between
+ * calls in FP64 exactly as vofl_step carries it between steps, so a run of
+ * n steps split into any advance calls equals vofl_step's n steps bit for
+ * bit (2D/3D; in 1D each advance is a vofl_step on the run's own copy of
+ * (u, v), which matches a single vofl_step to rounding).
+ * vofl_step_end: writes the run's current (u, v) (device, batch * N values
+ * each, u != v) and leaves the run open: advance may continue afterwards.
+ * Each call costs the steps it advances: no re-import per call (one extra
+ * last-axis pass at the start of each advance and a light one at its end,
+ * in place of vofl_step's merged half steps).
+ * A run ends when any other call (vofl_apply, vofl_step, vofl_step_graph,
+ * vofl_lffp_*, vofl_cnfp_step, vofl_step_batch) uses the plan; advance and
+ * end then fail with VOFL_ERR_INVALID until the next begin. All three are
+ * asynchronous on stream; calls on one plan must be issued on one stream or
+ * ordered with events (they share the plan's buffers). */
+int vofl_step_begin(vofl_plan_t plan, const void* u, const void* v, void* stream);
+int vofl_step_advance(vofl_plan_t plan, int nsteps, int use_graph, void* stream);
+int vofl_step_end(vofl_plan_t plan, void* u, void* v, void* stream);
 
 /* u = u0, v = v0, then nsteps steps as vofl_step. u0/v0 may equal u/v. */
 int vofl_solve(vofl_plan_t plan, const void* u0, const void* v0, int nsteps,

@@ -31,7 +31,9 @@
 
 namespace vofl {
 
-enum InKind : int { IN_APPLY = 0, IN_INIT = 1, IN_KICK = 2 };
+// IN_STATE: the spectral state (u_hat, v_hat) itself is the input (no
+// transform), for steps resumed from the plan's state.
+enum InKind : int { IN_APPLY = 0, IN_INIT = 1, IN_KICK = 2, IN_STATE = 3 };
 enum EmitKind : int { EMIT_NONE = 0, EMIT_APPLY = 1, EMIT_STEP = 2, EMIT_EXPORT = 3, EMIT_GENERIC = 4 };
 enum C2RMode : int { C2R_APPLY = 0, C2R_KICK = 1, C2R_EXPORT = 2, C2R_KICK_GENERIC = 3 };
 enum ModelKind : int { MODEL_SEISMIC = 0, MODEL_GENERIC = 1 };
@@ -185,6 +187,7 @@ struct ContigArgs {
     const SolveScalars* sc;  // per item (sc_stride 1) or shared (0)
     int sc_stride;
     int in_kind, emit_kind, do_prop, M, op;
+    int no_store;            // 1: leave the spectral state unchanged (IN_STATE exports)
     double tprop, dt, invN;
 };
 
@@ -230,7 +233,15 @@ __global__ __launch_bounds__(P*(N / E)) void k_contig(ContigArgs<T, TI> a) {
     };
 
     cpx<double> uh[E], vh[E];
-    if (a.in_kind == IN_KICK) {
+    if (a.in_kind == IN_STATE) {
+        const cpx<double>* Us = a.U + (long long)bi * a.H + pen;
+        const cpx<double>* Vs = a.V + (long long)bi * a.H + pen;
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+            uh[e] = Us[t + TP * e];
+            vh[e] = Vs[t + TP * e];
+        }
+    } else if (a.in_kind == IN_KICK) {
         cpx<TI> d[E];
         const cpx<TI>* src = a.in + (long long)bi * a.in_istride + pen;
 #pragma unroll
@@ -270,7 +281,7 @@ __global__ __launch_bounds__(P*(N / E)) void k_contig(ContigArgs<T, TI> a) {
     double L[E];
     cpx<double>* Ud = a.U + (long long)bi * a.H + pen;
     cpx<double>* Vd = a.V + (long long)bi * a.H + pen;
-    const bool store_state = (a.in_kind != IN_APPLY) && active;
+    const bool store_state = (a.in_kind != IN_APPLY) && !a.no_store && active;
 #pragma unroll
     for (int e = 0; e < E; ++e) {
         const double m2 = m2base + a.mu2_l[t + TP * e];
@@ -560,9 +571,12 @@ __device__ __forceinline__ cpx<T> hermitian_pair(const cpx<T>* h1, const cpx<T>*
 
 // Transforms of one k_c2r0 launch: transform i reads the slot pair
 // (2i, 2i+1); the second slot is absent (-1) past the last slot.
+// The export transforms u and v one at a time: v is far smaller than u
+// early in a solve (v0 = 0), and a shared complex transform would add
+// rounding relative to u to it.
 __device__ __forceinline__ int c2r_transforms(int mode, int M) {
     switch (mode) {
-        case C2R_EXPORT: return 1;
+        case C2R_EXPORT: return 2;
         case C2R_APPLY: return (M + 2) / 2;         // slots 0..M
         case C2R_KICK: return M + 1;                // slots 0..2M+1
         default: return (M + 3) / 2;                // generic: slots 0..M+1
@@ -661,8 +675,8 @@ void k_c2r0(C2RArgs<T> a) {
     // on the pair index and the compiler can keep PD pairs in flight.
     auto load_pair = [&](int tr, cpx<T> (&q1)[E], cpx<T> (&q2)[E]) __attribute__((always_inline)) {
         const bool live = tr < nT;
-        const int s1 = live ? 2 * tr : 0;
-        const int s2 = live ? min(2 * tr + 1, nS - 1) : 0;
+        const int s1 = live ? (MODE == C2R_EXPORT ? tr : 2 * tr) : 0;
+        const int s2 = live ? (MODE == C2R_EXPORT ? tr : min(2 * tr + 1, nS - 1)) : 0;
         const unsigned bytes = live ? unsigned(a.H * (long long)sizeof(cpx<T>)) : 0u;
         const auto r1 = make_rsrc(ibase + (long long)s1 * a.H, bytes);
         const auto r2 = make_rsrc(ibase + (long long)s2 * a.H, bytes);
@@ -784,6 +798,7 @@ void k_c2r0(C2RArgs<T> a) {
     constexpr bool SPLIT = MODE == C2R_KICK && sizeof(T) == 4 && E <= 8;
     T acc[E], cA[E], cB[E];
     T S1[SPLIT ? E : 1], S2[SPLIT ? E : 1];
+    T ux[MODE == C2R_EXPORT ? E : 1];  // export: u from the first transform
     double dm[E];
     cpx<T> y[E];
 #pragma unroll
@@ -811,7 +826,12 @@ void k_c2r0(C2RArgs<T> a) {
     // transform tr of the pair held in y: inverse axis-0 FFT and accumulation
     auto transform = [&](int tr) __attribute__((always_inline)) {
         fft(y, std::integral_constant<int, +1>{});
-        if constexpr (MODE == C2R_APPLY) {
+        if constexpr (MODE == C2R_EXPORT) {
+            if (tr == 0) {
+#pragma unroll
+                for (int e = 0; e < E; ++e) ux[e] = y[e].x;
+            }
+        } else if constexpr (MODE == C2R_APPLY) {
 #pragma unroll
             for (int e = 0; e < E; ++e) {
                 const double d = dl[e];
@@ -878,7 +898,7 @@ void k_c2r0(C2RArgs<T> a) {
 #pragma unroll
         for (int d = 0; d < PD; ++d) {
             const int tr = base + d;
-            build(y, p1[d], p2[d], 2 * tr + 1 < nS);
+            build(y, p1[d], p2[d], MODE != C2R_EXPORT && 2 * tr + 1 < nS);
             __builtin_amdgcn_sched_barrier(0);
             load_pair(tr + PD, p1[d], p2[d]);  // in flight during the next transforms
             __builtin_amdgcn_sched_barrier(0);
@@ -892,8 +912,8 @@ void k_c2r0(C2RArgs<T> a) {
             T* v = a.r1 + (long long)item * a.Nreal + colc;
 #pragma unroll
             for (int e = 0; e < E; ++e) {
-                u[(long long)(t + TP * e) * a.inner] = y[e].x;
-                v[(long long)(t + TP * e) * a.inner] = y[e].y;
+                u[(long long)(t + TP * e) * a.inner] = ux[e];
+                v[(long long)(t + TP * e) * a.inner] = y[e].x;
             }
         }
         return;
@@ -1464,16 +1484,17 @@ __global__ __launch_bounds__(N / E) void k_1d_step(Args1D<T> a) {
         propagate(s + 1 < K ? 0.5 * (ds + substep_len(a.dt, a.sub, a.w1, a.w0, s + 1)) : 0.5 * ds);
     }
     if (bad) a.flag[0] = 1;
-    cpx<T> y[E];
-#pragma unroll
-    for (int e = 0; e < E; ++e) y[e] = {T(uh[e].x - vh[e].y), T(uh[e].y + vh[e].x)};
-    fft_pencil<T, N, E, +1>(y, t, lds, tw_s);
+    // u and v transformed one at a time (v can be far smaller than u)
     T* uo = a.u_out + (long long)item * N;
     T* vo = a.v_out + (long long)item * N;
+    for (int f = 0; f < 2; ++f) {
+        cpx<T> y[E];
 #pragma unroll
-    for (int e = 0; e < E; ++e) {
-        uo[t + TP * e] = y[e].x;
-        vo[t + TP * e] = y[e].y;
+        for (int e = 0; e < E; ++e) y[e] = from_d<T>(f == 0 ? uh[e] : vh[e]);
+        fft_pencil<T, N, E, +1>(y, t, lds, tw_s);
+        T* o = f == 0 ? uo : vo;
+#pragma unroll
+        for (int e = 0; e < E; ++e) o[t + TP * e] = y[e].x;
     }
 }
 

@@ -69,9 +69,22 @@ bool contig_streams(const ContigArgs<T, TI>& a, int items) {
     return 2LL * (a.M + 1) * a.H * (long long)sizeof(cpx<T>) * items > (256LL << 20);
 }
 
+// Pointers every k_contig launch dereferences whatever its kind (the
+// twiddle tables are staged into LDS at the start, the symbol tables and the
+// scalars are read per element), and those its input and output kinds need.
+template <typename T, typename TI>
+bool contig_args_ok(const ContigArgs<T, TI>& a) {
+    if (!a.tw || !a.tw_in || !a.mu2_0 || !a.mu2_l || !a.sc) return false;
+    if ((a.in_kind == IN_INIT || a.in_kind == IN_KICK || a.in_kind == IN_APPLY) && !a.in) return false;
+    if (a.in_kind != IN_APPLY && (!a.U || !a.V)) return false;
+    if (a.emit_kind != EMIT_NONE && !a.out) return false;
+    return true;
+}
+
 template <typename T>
 template <typename TI>
 hipError_t Launch<T>::contig(int N, const ContigArgs<T, TI>& a, int items, hipStream_t s) {
+    if (!contig_args_ok(a)) return hipErrorInvalidValue;
     switch (N) {
 #define C_(n)                                                                           \
     case n: {                                                                           \

@@ -177,6 +177,8 @@ int derive(const vofl_desc* d, Geometry& g) {
         // FP64 leap-frog state (u^{n-1}, u^n)
         bytes += (size_t)lffp_fields(d->model) * g.batch * g.Nreal * 8;
     }
+    else
+        bytes += (size_t)2 * g.batch * g.Nreal * g.elt;      // 1D resumable run: (u, v) between calls
     if (d->model == VOFL_MODEL_GENERIC)
         bytes += (size_t)CN_VECTORS * g.Nreal * g.elt + CN_SCALARS * 8;  // Crank-Nicolson solver vectors
     g.bytes = bytes;
@@ -238,6 +240,16 @@ struct vofl_plan_s {
     };
     std::vector<GraphEntry> graphs;    // vofl_step_graph cache, oldest first
     int mid_variant = 1;               // k_mid tile variant (1: double-width tiles)
+    // resumable run (vofl_step_begin / advance / end): 0 none; 1 the state is
+    // (u_hat, v_hat) at t_n itself (after begin); 2 the state is the one right
+    // after the kick of the last step (the step's closing half sub-step pending)
+    int run = 0;
+    long long run_steps = 0;           // steps advanced since begin
+    struct RunGraph {
+        int nsteps, phase;
+        hipGraphExec_t exec;
+    };
+    std::vector<RunGraph> run_graphs;  // vofl_step_advance graph cache, oldest first
     hipStream_t own_stream = nullptr;  // used by vofl_step_batch
     hipEvent_t fork_ev = nullptr, join_ev = nullptr;
     // timing
@@ -254,6 +266,7 @@ struct vofl_plan_s {
         }
         for (auto e : pool) (void)hipEventDestroy(e);
         for (auto& gr : graphs) (void)hipGraphExecDestroy(gr.exec);
+        for (auto& gr : run_graphs) (void)hipGraphExecDestroy(gr.exec);
         if (fork_ev) (void)hipEventDestroy(fork_ev);
         if (join_ev) (void)hipEventDestroy(join_ev);
         if (own_stream) (void)hipStreamDestroy(own_stream);
@@ -396,6 +409,10 @@ int upload_tables(vofl_plan_s* p, const std::vector<double>& delta, const std::v
         p->V = (cpx<double>*)p->U + (size_t)g.batch * g.H;
         if ((rc = dalloc(p, &p->LS, (size_t)lffp_fields(p->model) * g.batch * g.Nreal * sizeof(double))))
             return rc;
+    } else {
+        // 1D resumable run: the fields (u, v) of every solve between calls
+        if ((rc = dalloc(p, (T**)&p->U, (size_t)2 * g.batch * g.Nreal * sizeof(T)))) return rc;
+        p->V = (T*)p->U + (size_t)g.batch * g.Nreal;
     }
     if (p->model == VOFL_MODEL_GENERIC) {
         if ((rc = dalloc(p, (T**)&p->cnv, (size_t)CN_VECTORS * g.Nreal * sizeof(T)))) return rc;
@@ -424,6 +441,9 @@ ContigArgs<T, TI> contig_base(vofl_plan_s* p) {
     a.mu2_1 = (g.ndim == 3) ? p->mu2[1] : nullptr;
     a.mu2_l = p->mu2[g.ndim - 1];
     a.tw = (const cpx<T>*)p->tw[g.ndim - 1];
+    // input-transform twiddles: every launch stages them, whatever it reads
+    if constexpr (std::is_same<TI, double>::value) a.tw_in = p->tw64[g.ndim - 1];
+    else a.tw_in = (const cpx<TI>*)p->tw[g.ndim - 1];
     a.sc = p->sc + sc_off(p);
     a.sc_stride = g.ncoef > 1 ? 1 : 0;
     a.U = (cpx<double>*)p->U;
@@ -715,6 +735,129 @@ int step_multi(vofl_plan_s* p, T* u, T* v, int nsteps, hipStream_t s) {
     return VOFL_OK;
 }
 
+// Resumable run (2D/3D). The state between calls is kept in the plan's
+// FP64 spectral blocks: after begin, (u_hat, v_hat) at t_0; after advance,
+// the state right after the kick of the last step, whose closing exact half
+// sub-step (3.13) is applied by the next advance (merged with the next
+// step's opening half, as inside vofl_step) or by end (for the export only).
+// The arithmetic is that of vofl_step: the state passes through memory in
+// FP64 where vofl_step keeps it in registers, so a run of n steps in any
+// number of advance calls gives vofl_step's result for n steps bit for bit.
+template <typename T>
+int run_begin_multi(vofl_plan_s* p, const T* u, const T* v, hipStream_t s) {
+    const Geometry& g = p->g;
+    const int items = g.batch;
+    cpx<double>* U = (cpx<double>*)p->U;
+    cpx<double>* V = (cpx<double>*)p->V;
+    hipError_t e;
+    if ((e = forward_to_stage<T>(p, u, U, items, s)) != hipSuccess) return hip_fail(e, "r2c0 launch");
+    if ((e = forward_to_stage<T>(p, v, V, items, s)) != hipSuccess) return hip_fail(e, "r2c0 launch");
+    if ((e = mid<double>(p, "mid_init", -1, U, g.H, 1, 2 * items, p->tw64[1 % g.ndim], s)) != hipSuccess)
+        return hip_fail(e, "mid launch");
+    ContigArgs<T, double> a = contig_base<T, double>(p);
+    a.in = U;
+    a.in_istride = g.H;
+    a.in_fstride = (long long)items * g.H;
+    a.nin = 2;
+    a.tw_in = p->tw64[g.ndim - 1];
+    a.out = (cpx<T>*)p->work;
+    a.out_istride = (long long)g.step_slots * g.H;
+    a.in_kind = IN_INIT;
+    a.emit_kind = EMIT_NONE;
+    a.do_prop = 0;
+    e = p->timed("contig_begin", s, [&] { return Launch<T>::contig(g.nlast, a, items, s); });
+    return e == hipSuccess ? VOFL_OK : hip_fail(e, "contig launch");
+}
+
+template <typename T>
+int run_advance_multi(vofl_plan_s* p, int nsteps, int phase, hipStream_t s) {
+    if (nsteps == 0) return VOFL_OK;
+    const Geometry& g = p->g;
+    const long long SS = (long long)g.step_slots * g.H;
+    const int nterm = g.nterm;
+    const int dv = nterm;
+    const int items = g.batch;
+    const int emit_terms = p->model == VOFL_MODEL_GENERIC ? EMIT_GENERIC : EMIT_STEP;
+    cpx<T>* W = (cpx<T>*)p->work;
+    const cpx<T>* twm = (const cpx<T>*)p->tw[1 % g.ndim];
+    hipError_t e;
+    // reopen: the pending half sub-step(s) from the state, then the terms
+    {
+        ContigArgs<T, T> a = contig_base<T, T>(p);
+        a.out = W;
+        a.out_istride = SS;
+        a.in_kind = IN_STATE;
+        a.emit_kind = emit_terms;
+        a.do_prop = 1;
+        const double first = substep_len_h(p, 0);
+        a.tprop = phase == 1 ? 0.5 * first : 0.5 * (substep_len_h(p, p->sub - 1) + first);
+        e = p->timed("contig_resume", s, [&] { return Launch<T>::contig(g.nlast, a, items, s); });
+        if (e != hipSuccess) return hip_fail(e, "contig launch");
+    }
+    C2RArgs<T> c = c2r_base<T>(p);
+    c.in = W;
+    c.istride = SS;
+    c.mode = p->model == VOFL_MODEL_GENERIC ? C2R_KICK_GENERIC : C2R_KICK;
+    c.dv_out = W + (long long)dv * g.H;
+    ContigArgs<T, T> a = contig_base<T, T>(p);
+    a.in = W + (long long)dv * g.H;
+    a.in_istride = SS;
+    a.nin = 1;
+    a.tw_in = (const cpx<T>*)p->tw[g.ndim - 1];
+    a.out = W;
+    a.out_istride = SS;
+    a.in_kind = IN_KICK;
+    const int K = nsteps * p->sub;
+    for (int st = 0; st < K; ++st) {
+        const bool last = (st + 1 == K);
+        const double ds = substep_len_h(p, st);
+        a.dt = ds;
+        if ((e = mid<T>(p, "mid_terms", +1, W, SS, nterm, items, twm, s)) != hipSuccess) return hip_fail(e, "mid launch");
+        e = p->timed("c2r0_kick", s, [&] { return Launch<T>::c2r0(g.n[0], c, items, s, p->c2r_variant); });
+        if (e != hipSuccess) return hip_fail(e, "c2r0 launch");
+        if ((e = mid<T>(p, "mid_dv", -1, W + (long long)dv * g.H, SS, 1, items, twm, s)) != hipSuccess)
+            return hip_fail(e, "mid launch");
+        // the last kick of the call stores the state and stops there
+        a.do_prop = last ? 0 : 1;
+        a.tprop = last ? 0.0 : 0.5 * (ds + substep_len_h(p, st + 1));
+        a.emit_kind = last ? EMIT_NONE : emit_terms;
+        e = p->timed(last ? "contig_close" : "contig_kick", s, [&] { return Launch<T>::contig(g.nlast, a, items, s); });
+        if (e != hipSuccess) return hip_fail(e, "contig launch");
+    }
+    return VOFL_OK;
+}
+
+template <typename T>
+int run_end_multi(vofl_plan_s* p, T* u, T* v, int phase, hipStream_t s) {
+    const Geometry& g = p->g;
+    const long long SS = (long long)g.step_slots * g.H;
+    const int h0 = g.nterm + 1;
+    const int items = g.batch;
+    cpx<T>* W = (cpx<T>*)p->work;
+    const cpx<T>* twm = (const cpx<T>*)p->tw[1 % g.ndim];
+    hipError_t e;
+    ContigArgs<T, T> a = contig_base<T, T>(p);
+    a.out = W + (long long)h0 * g.H;
+    a.out_istride = SS;
+    a.in_kind = IN_STATE;
+    a.no_store = 1;
+    a.emit_kind = EMIT_EXPORT;
+    a.do_prop = phase == 2 ? 1 : 0;
+    a.tprop = 0.5 * substep_len_h(p, p->sub - 1);
+    e = p->timed("contig_end", s, [&] { return Launch<T>::contig(g.nlast, a, items, s); });
+    if (e != hipSuccess) return hip_fail(e, "contig launch");
+    if ((e = mid<T>(p, "mid_export", +1, W + (long long)h0 * g.H, SS, 2, items, twm, s)) != hipSuccess)
+        return hip_fail(e, "mid launch");
+    C2RArgs<T> x = c2r_base<T>(p);
+    x.in = W + (long long)h0 * g.H;
+    x.istride = SS;
+    x.mode = C2R_EXPORT;
+    x.r0 = u;
+    x.r1 = v;
+    e = p->timed("c2r0_export", s, [&] { return Launch<T>::c2r0(g.n[0], x, items, s, p->c2r_variant); });
+    return e == hipSuccess ? VOFL_OK : hip_fail(e, "c2r0 launch");
+}
+
 template <typename T>
 Args1D<T> args_1d(vofl_plan_s* p) {
     const Geometry& g = p->g;
@@ -927,6 +1070,33 @@ int step_any(vofl_plan_s* p, void* u, void* v, int nsteps, hipStream_t s) {
     hipError_t e = p->timed("1d_step", s, [&] { return Launch<T>::d1_step(a.N, a, p->g.batch, s); });
     if (e != hipSuccess) return hip_fail(e, "1d step launch");
     return VOFL_OK;
+}
+
+// Resumable run in 1D: (u, v) are kept in the plan's run buffers between
+// calls, and every advance is one vofl_step on them (the 1D step kernel
+// keeps the spectral state in registers within a call).
+template <typename T>
+int run_begin_any(vofl_plan_s* p, const void* u, const void* v, hipStream_t s) {
+    if (p->g.ndim >= 2) return run_begin_multi<T>(p, (const T*)u, (const T*)v, s);
+    const size_t bytes = (size_t)p->g.batch * p->g.Nreal * sizeof(T);
+    hipError_t e = hipMemcpyAsync(p->U, u, bytes, hipMemcpyDeviceToDevice, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(p->V, v, bytes, hipMemcpyDeviceToDevice, s);
+    return e == hipSuccess ? VOFL_OK : hip_fail(e, "run copy");
+}
+
+template <typename T>
+int run_advance_any(vofl_plan_s* p, int nsteps, int phase, hipStream_t s) {
+    if (p->g.ndim >= 2) return run_advance_multi<T>(p, nsteps, phase, s);
+    return step_any<T>(p, p->U, p->V, nsteps, s);
+}
+
+template <typename T>
+int run_end_any(vofl_plan_s* p, void* u, void* v, int phase, hipStream_t s) {
+    if (p->g.ndim >= 2) return run_end_multi<T>(p, (T*)u, (T*)v, phase, s);
+    const size_t bytes = (size_t)p->g.batch * p->g.Nreal * sizeof(T);
+    hipError_t e = hipMemcpyAsync(u, p->U, bytes, hipMemcpyDeviceToDevice, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(v, p->V, bytes, hipMemcpyDeviceToDevice, s);
+    return e == hipSuccess ? VOFL_OK : hip_fail(e, "run copy");
 }
 
 }  // namespace
@@ -1179,6 +1349,7 @@ int vofl_destroy(vofl_plan_t plan) {
 
 int vofl_apply(vofl_plan_t p, int op, const void* u, void* out, int nfields, void* stream) {
     if (!p) return fail(VOFL_ERR_INVALID, "plan is NULL");
+    p->run = 0;  // these calls reuse the buffers that hold a resumable run
     if (!u || !out) return fail(VOFL_ERR_INVALID, "u and out must be device pointers");
     if (u == out) return fail(VOFL_ERR_INVALID, "out must not alias u");
     if (op != VOFL_OP_S1 && op != VOFL_OP_S2) return fail(VOFL_ERR_INVALID, "op must be VOFL_OP_S1 or VOFL_OP_S2");
@@ -1194,6 +1365,7 @@ int vofl_apply(vofl_plan_t p, int op, const void* u, void* out, int nfields, voi
 
 int vofl_step(vofl_plan_t p, void* u, void* v, int nsteps, void* stream) {
     if (!p) return fail(VOFL_ERR_INVALID, "plan is NULL");
+    p->run = 0;  // these calls reuse the buffers that hold a resumable run
     if (!u || !v) return fail(VOFL_ERR_INVALID, "u and v must be device pointers");
     if (u == v) return fail(VOFL_ERR_INVALID, "u and v must be distinct");
     if (nsteps < 0) return fail(VOFL_ERR_INVALID, "nsteps must be >= 0");
@@ -1204,6 +1376,7 @@ int vofl_step(vofl_plan_t p, void* u, void* v, int nsteps, void* stream) {
 
 int vofl_step_graph(vofl_plan_t p, void* u, void* v, int nsteps, void* stream) {
     if (!p) return fail(VOFL_ERR_INVALID, "plan is NULL");
+    p->run = 0;  // these calls reuse the buffers that hold a resumable run
     if (!u || !v) return fail(VOFL_ERR_INVALID, "u and v must be device pointers");
     if (u == v) return fail(VOFL_ERR_INVALID, "u and v must be distinct");
     if (nsteps < 0) return fail(VOFL_ERR_INVALID, "nsteps must be >= 0");
@@ -1250,6 +1423,88 @@ int vofl_step_graph(vofl_plan_t p, void* u, void* v, int nsteps, void* stream) {
     return e == hipSuccess ? VOFL_OK : hip_fail(e, "graph launch");
 }
 
+int vofl_step_begin(vofl_plan_t p, const void* u, const void* v, void* stream) {
+    if (!p) return fail(VOFL_ERR_INVALID, "plan is NULL");
+    if (!u || !v) return fail(VOFL_ERR_INVALID, "u and v must be device pointers");
+    p->run = 0;
+    hipStream_t s = (hipStream_t)stream;
+    const int rc = p->precision == VOFL_FP32 ? run_begin_any<float>(p, u, v, s) : run_begin_any<double>(p, u, v, s);
+    if (rc) return rc;
+    p->run = 1;
+    p->run_steps = 0;
+    return VOFL_OK;
+}
+
+int vofl_step_advance(vofl_plan_t p, int nsteps, int use_graph, void* stream) {
+    if (!p) return fail(VOFL_ERR_INVALID, "plan is NULL");
+    if (!p->run) return fail(VOFL_ERR_INVALID, "no run in progress (call vofl_step_begin first)");
+    if (nsteps < 0) return fail(VOFL_ERR_INVALID, "nsteps must be >= 0");
+    if (nsteps == 0) return VOFL_OK;
+    hipStream_t s = (hipStream_t)stream;
+    const int phase = p->run;
+    auto launch = [&](hipStream_t st) {
+        return p->precision == VOFL_FP32 ? run_advance_any<float>(p, nsteps, phase, st)
+                                         : run_advance_any<double>(p, nsteps, phase, st);
+    };
+    int rc = VOFL_OK;
+    if (!use_graph) {
+        rc = launch(s);
+    } else {
+        hipGraphExec_t exec = nullptr;
+        for (auto& gr : p->run_graphs)
+            if (gr.nsteps == nsteps && gr.phase == phase) exec = gr.exec;
+        if (!exec) {
+            hipError_t e = hipSuccess;
+            if (!p->own_stream) {
+                e = hipStreamCreateWithFlags(&p->own_stream, hipStreamNonBlocking);
+                if (e == hipSuccess) e = hipEventCreateWithFlags(&p->join_ev, hipEventDisableTiming);
+                if (e != hipSuccess) return hip_fail(e, "stream");
+            }
+            const bool timing = p->timing;
+            p->timing = false;  // no event records inside the graph
+            e = hipStreamBeginCapture(p->own_stream, hipStreamCaptureModeThreadLocal);
+            if (e != hipSuccess) {
+                p->timing = timing;
+                return hip_fail(e, "begin capture");
+            }
+            rc = launch(p->own_stream);
+            hipGraph_t graph = nullptr;
+            e = hipStreamEndCapture(p->own_stream, &graph);
+            p->timing = timing;
+            if (rc) {
+                if (graph) (void)hipGraphDestroy(graph);
+                return rc;
+            }
+            if (e != hipSuccess) return hip_fail(e, "end capture");
+            e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+            (void)hipGraphDestroy(graph);
+            if (e != hipSuccess) return hip_fail(e, "graph instantiate");
+            if (p->run_graphs.size() >= 8) {
+                (void)hipDeviceSynchronize();  // the oldest graph may still be running
+                (void)hipGraphExecDestroy(p->run_graphs.front().exec);
+                p->run_graphs.erase(p->run_graphs.begin());
+            }
+            p->run_graphs.push_back({nsteps, phase, exec});
+        }
+        hipError_t e = hipGraphLaunch(exec, s);
+        if (e != hipSuccess) return hip_fail(e, "graph launch");
+    }
+    if (rc) return rc;
+    p->run = 2;
+    p->run_steps += nsteps;
+    return VOFL_OK;
+}
+
+int vofl_step_end(vofl_plan_t p, void* u, void* v, void* stream) {
+    if (!p) return fail(VOFL_ERR_INVALID, "plan is NULL");
+    if (!p->run) return fail(VOFL_ERR_INVALID, "no run in progress (call vofl_step_begin first)");
+    if (!u || !v) return fail(VOFL_ERR_INVALID, "u and v must be device pointers");
+    if (u == v) return fail(VOFL_ERR_INVALID, "u and v must be distinct");
+    hipStream_t s = (hipStream_t)stream;
+    return p->precision == VOFL_FP32 ? run_end_any<float>(p, u, v, p->run, s)
+                                     : run_end_any<double>(p, u, v, p->run, s);
+}
+
 int vofl_solve(vofl_plan_t p, const void* u0, const void* v0, int nsteps, void* u, void* v, void* stream) {
     if (!p) return fail(VOFL_ERR_INVALID, "plan is NULL");
     if (!u0 || !v0 || !u || !v) return fail(VOFL_ERR_INVALID, "null device pointer");
@@ -1264,6 +1519,7 @@ int vofl_solve(vofl_plan_t p, const void* u0, const void* v0, int nsteps, void* 
 
 int vofl_lffp_start(vofl_plan_t p, const void* phi, const void* psi, void* u_prev, void* u, void* stream) {
     if (!p) return fail(VOFL_ERR_INVALID, "plan is NULL");
+    p->run = 0;  // these calls reuse the buffers that hold a resumable run
     if (!phi || !psi || !u_prev || !u) return fail(VOFL_ERR_INVALID, "phi, psi, u_prev and u must be device pointers");
     if (u_prev == u) return fail(VOFL_ERR_INVALID, "u_prev and u must be distinct");
     hipStream_t s = (hipStream_t)stream;
@@ -1276,6 +1532,7 @@ int vofl_lffp_start(vofl_plan_t p, const void* phi, const void* psi, void* u_pre
 
 int vofl_lffp_step(vofl_plan_t p, void* u_prev, void* u, int nsteps, void* stream) {
     if (!p) return fail(VOFL_ERR_INVALID, "plan is NULL");
+    p->run = 0;  // these calls reuse the buffers that hold a resumable run
     if (!u_prev || !u) return fail(VOFL_ERR_INVALID, "u_prev and u must be device pointers");
     if (u_prev == u) return fail(VOFL_ERR_INVALID, "u_prev and u must be distinct");
     if (nsteps < 0) return fail(VOFL_ERR_INVALID, "nsteps must be >= 0");
@@ -1290,6 +1547,7 @@ int vofl_lffp_step(vofl_plan_t p, void* u_prev, void* u, int nsteps, void* strea
 int vofl_cnfp_step(vofl_plan_t p, void* u_prev, void* u, int nsteps, double tol, int max_iter,
                    long long* iterations, void* stream) {
     if (!p) return fail(VOFL_ERR_INVALID, "plan is NULL");
+    p->run = 0;  // these calls reuse the buffers that hold a resumable run
     if (!u_prev || !u) return fail(VOFL_ERR_INVALID, "u_prev and u must be device pointers");
     if (u_prev == u) return fail(VOFL_ERR_INVALID, "u_prev and u must be distinct");
     if (nsteps < 0) return fail(VOFL_ERR_INVALID, "nsteps must be >= 0");

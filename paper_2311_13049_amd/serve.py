@@ -8,8 +8,10 @@ owns a HIP stream: its plan is built, its fields are uploaded from pinned
 host memory, and it is advanced in chunks of TSFP2 steps (each chunk a
 captured graph replay, vofl_step_graph) while other requests run on their own
 streams, so that their kernels overlap on the device. Wavefields stay
-resident in device memory for the whole solve; at the end (u, v) are copied
-back asynchronously and the stability flag is read.
+resident in device memory for the whole solve, and the solve's spectral
+state stays in its plan between chunks (vofl_step_begin, vofl_step_advance,
+vofl_step_end), so a chunk costs only its steps; at the end (u, v) are
+written out, copied back asynchronously and the stability flag is read.
 
 One host thread makes every HIP call: graph capture on one thread must not
 overlap device-wide calls (allocation, synchronisation, frees) made by
@@ -164,6 +166,7 @@ class _Job:
         self.done_ev = None
         self.step_s = est_step_seconds(req, precision)
         self.chunk = 1
+        self.resumable = False      # advanced through vofl_step_begin/advance/end
 
     def remaining_s(self) -> float:
         return (self.req.steps - self.issued) * self.step_s
@@ -179,7 +182,8 @@ class Server:
     slice_s      target device time of one chunk (chunk=None)
     queue_s      estimated device time that may be queued over all requests;
                  every running request may still keep one chunk queued
-    graphs       replay captured graphs for the chunks (vofl_step_graph)
+    graphs       replay captured graphs for the chunks (vofl_step_advance with
+                 use_graph; vofl_step_graph for a solve issued in one call)
     precision    force every request to this precision (None: the request's)
     keep_results download (u, v) of every request
     """
@@ -221,11 +225,17 @@ class Server:
             dev.copy_(host, non_blocking=True)
         job.host, job.dev = host, dev
         job.u, job.v = dev[0], dev[1]
+        if job.chunk < r.steps:
+            # chunked: the spectral state stays in the plan between chunks
+            V.vofl_step_begin(job.plan.handle, job.u.data_ptr(), job.v.data_ptr(), st.cuda_stream)
+            job.resumable = True
 
     def _launch(self, job: _Job, k: int) -> None:
         st = self.streams[job.slot]
         h = job.plan.handle
-        if self.graphs:
+        if job.resumable:
+            V.vofl_step_advance(h, k, 1 if self.graphs else 0, st.cuda_stream)
+        elif self.graphs:
             V.vofl_step_graph(h, job.u.data_ptr(), job.v.data_ptr(), k, st.cuda_stream)
         else:
             V.vofl_step(h, job.u.data_ptr(), job.v.data_ptr(), k, st.cuda_stream)
@@ -237,6 +247,8 @@ class Server:
     def _download(self, job: _Job) -> None:
         torch = self.torch
         st = self.streams[job.slot]
+        if job.resumable:
+            V.vofl_step_end(job.plan.handle, job.u.data_ptr(), job.v.data_ptr(), st.cuda_stream)
         if self.keep_results:
             with torch.cuda.stream(st):
                 job.host.copy_(job.dev, non_blocking=True)

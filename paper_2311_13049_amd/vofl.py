@@ -32,7 +32,8 @@ VOFL_OP_S2 = 2
 # every function declared in include/vofl.h
 ABI_FUNCTIONS = (
     "vofl_plan", "vofl_plan_footprint", "vofl_apply", "vofl_step", "vofl_step_graph", "vofl_solve",
-    "vofl_lffp_start", "vofl_lffp_step", "vofl_cnfp_step", "vofl_step_batch", "vofl_sync_status", "vofl_set_timing", "vofl_kernel_times",
+    "vofl_step_begin", "vofl_step_advance", "vofl_step_end", "vofl_lffp_start", "vofl_lffp_step",
+    "vofl_cnfp_step", "vofl_step_batch", "vofl_sync_status", "vofl_set_timing", "vofl_kernel_times",
     "vofl_plan_info", "vofl_destroy", "vofl_last_error", "vofl_version",
 )
 
@@ -90,6 +91,9 @@ def load_library():
     lib.vofl_apply.argtypes = [vp, ctypes.c_int, vp, vp, ctypes.c_int, vp]
     lib.vofl_step.argtypes = [vp, vp, vp, ctypes.c_int, vp]
     lib.vofl_step_graph.argtypes = [vp, vp, vp, ctypes.c_int, vp]
+    lib.vofl_step_begin.argtypes = [vp, vp, vp, vp]
+    lib.vofl_step_advance.argtypes = [vp, ctypes.c_int, ctypes.c_int, vp]
+    lib.vofl_step_end.argtypes = [vp, vp, vp, vp]
     lib.vofl_lffp_start.argtypes = [vp, vp, vp, vp, vp, vp]
     lib.vofl_lffp_step.argtypes = [vp, vp, vp, ctypes.c_int, vp]
     lib.vofl_cnfp_step.argtypes = [vp, vp, vp, ctypes.c_int, ctypes.c_double, ctypes.c_int,
@@ -106,7 +110,8 @@ def load_library():
     lib.vofl_last_error.restype = ctypes.c_char_p
     lib.vofl_version.restype = ctypes.c_char_p
     for name in ("vofl_plan", "vofl_plan_footprint", "vofl_apply", "vofl_step", "vofl_step_graph", "vofl_solve",
-                 "vofl_lffp_start", "vofl_lffp_step", "vofl_cnfp_step",
+                 "vofl_step_begin", "vofl_step_advance", "vofl_step_end", "vofl_lffp_start", "vofl_lffp_step",
+                 "vofl_cnfp_step",
                  "vofl_step_batch", "vofl_sync_status", "vofl_set_timing", "vofl_kernel_times",
                  "vofl_plan_info", "vofl_destroy"):
         getattr(lib, name).restype = ctypes.c_int
@@ -188,6 +193,21 @@ def vofl_step(plan: int, u_ptr: int, v_ptr: int, nsteps: int, stream=0) -> None:
 def vofl_step_graph(plan: int, u_ptr: int, v_ptr: int, nsteps: int, stream=0) -> None:
     _check(load_library().vofl_step_graph(ctypes.c_void_p(plan), ctypes.c_void_p(u_ptr),
                                           ctypes.c_void_p(v_ptr), nsteps, ctypes.c_void_p(stream)))
+
+
+def vofl_step_begin(plan: int, u_ptr: int, v_ptr: int, stream=0) -> None:
+    _check(load_library().vofl_step_begin(ctypes.c_void_p(plan), ctypes.c_void_p(u_ptr),
+                                          ctypes.c_void_p(v_ptr), ctypes.c_void_p(stream)))
+
+
+def vofl_step_advance(plan: int, nsteps: int, use_graph: int = 0, stream=0) -> None:
+    _check(load_library().vofl_step_advance(ctypes.c_void_p(plan), int(nsteps), int(use_graph),
+                                            ctypes.c_void_p(stream)))
+
+
+def vofl_step_end(plan: int, u_ptr: int, v_ptr: int, stream=0) -> None:
+    _check(load_library().vofl_step_end(ctypes.c_void_p(plan), ctypes.c_void_p(u_ptr),
+                                        ctypes.c_void_p(v_ptr), ctypes.c_void_p(stream)))
 
 
 def vofl_lffp_start(plan: int, phi_ptr: int, psi_ptr: int, u_prev_ptr: int, u_ptr: int, stream=0) -> None:
@@ -315,6 +335,23 @@ class Plan:
         self._check_tensor(u, self.batch, "u")
         self._check_tensor(v, self.batch, "v")
         vofl_step_graph(self.handle, u.data_ptr(), v.data_ptr(), int(nsteps), self._stream())
+        return u, v
+
+    def begin(self, u, v):
+        """vofl_step_begin: start a resumable run from (u, v) (read only)."""
+        self._check_tensor(u, self.batch, "u")
+        self._check_tensor(v, self.batch, "v")
+        vofl_step_begin(self.handle, u.data_ptr(), v.data_ptr(), self._stream())
+
+    def advance(self, nsteps: int, graph: bool = False):
+        """vofl_step_advance: nsteps steps of the run (graph: replay a captured graph)."""
+        vofl_step_advance(self.handle, int(nsteps), 1 if graph else 0, self._stream())
+
+    def end(self, u, v):
+        """vofl_step_end: write the run's current (u, v) into the given tensors."""
+        self._check_tensor(u, self.batch, "u")
+        self._check_tensor(v, self.batch, "v")
+        vofl_step_end(self.handle, u.data_ptr(), v.data_ptr(), self._stream())
         return u, v
 
     def lffp_start(self, phi, psi):
