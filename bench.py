@@ -1,8 +1,11 @@
 """Benchmark: TSFP2 steps of the viscoacoustic model (1.1) on a 256^3 grid,
-M = 16, FP32 transforms (FP64 expansion coefficients, multipliers,
-propagator and spectral state), one MI355X.
+M = 16, one MI355X. The headline line is the FP64 path (the paper's
+arithmetic); the FP32 form (FP32 transforms with FP64 expansion
+coefficients, multipliers, propagator and spectral state) is measured in the
+same run and reported beside it with its own roofline.
 
-python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--workload c3|c4|c5]
+python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--precision fp64|fp32]
+                [--workload c3|c2|c4|c5|lffp|ex3]
 
 The default workload (c3) is the 256^3 grid below. Two more measurements
 print their own JSON line: c4, the batched shots (64 x 512^2 sharing one Q
@@ -77,12 +80,14 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--n", type=int, default=256)
     ap.add_argument("--M", type=int, default=16)
-    ap.add_argument("--precision", default="fp32")
+    ap.add_argument("--precision", default=None,
+                    help="c3 (default fp64, the paper's arithmetic): the headline path, with the other precision "
+                         "measured beside it; lffp, ex3 (default fp32)")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-extras", action="store_true",
                     help="c3: skip the step-time spread and the b = 1, 4 apply rates (profiling runs)")
     ap.add_argument("--workload", default="c3", choices=("c3", "c2", "c4", "c5", "lffp", "ex3"))
-    ap.add_argument("--requests", type=int, default=40, help="c5: requests in the trace")
+    ap.add_argument("--requests", type=int, default=200, help="c5: requests in the trace")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain device copy of 1 GiB five times (HBM counter calibration)")
     args = ap.parse_args()
@@ -98,6 +103,8 @@ def main():
 
     assert torch.cuda.is_available(), "bench needs a GPU"
     dev = torch.device("cuda:0")
+    if args.precision is None:
+        args.precision = "fp64" if args.workload == "c3" else "fp32"
     if args.calibrate_copy:
         nbytes = 1 << 30
         a = torch.empty(nbytes // 4, dtype=torch.float32, device=dev).fill_(1.0)
@@ -132,7 +139,106 @@ def main():
         return bench_c2(args, torch, V, dev)
     n, M = args.n, args.M
     c = c3_inputs(n=n)
+    if args.precision not in ("fp64", "fp32"):
+        raise SystemExit("--precision must be fp64 or fp32")
+    other = "fp32" if args.precision == "fp64" else "fp64"
+    head = _c3_measure(args, torch, V, dev, c, args.precision, extras=not args.no_extras)
+    side = None if args.no_extras else _c3_measure(args, torch, V, dev, c, other, extras=True)
+    N = n ** 3
+
+    cpu = None
+    cpu_mt = None
+    accuracy = None
+    if not args.no_cpu:
+        import oracle as O
+        gamma = O.gamma_from_Q(c["Q"])
+        x = c["u0"]
+        t0 = time.perf_counter()
+        O.mterm_apply(x, 1.0 + gamma, c["lo"], c["hi"], M)
+        cpu_s = time.perf_counter() - t0
+        cpu = {"value": 1.0 / cpu_s, "unit": "applies/s", "cores": 1, "kind": "oracle",
+               "sample": f"one oracle apply (2.13) of L1 on the {n}^3 M={M} field, FP64 numpy "
+                         f"(pocketfft, single thread): {cpu_s:.1f} s"}
+        # accuracy of the benchmarked plans: L1 of the workload's initial field
+        # (rounded to FP32, so that both precisions see the same values)
+        # against the FP64 oracle evaluated point by point
+        x_seen = c["u0"].astype(np.float32).astype(np.float64)
+        rng = np.random.default_rng(np.random.SeedSequence(13049 + 3, spawn_key=(95,)))
+        pts = [tuple(k // 2 for k in c["shape"])] + [tuple(int(rng.integers(k)) for k in c["shape"]) for _ in range(5)]
+        t0 = time.perf_counter()
+        ref = O.mterm_apply_at(x_seen, 1.0 + gamma, c["lo"], c["hi"], M, pts)
+        acc_s = time.perf_counter() - t0
+        accuracy = {"points": len(pts), "operator": "L1 = (-Lap)^{1+gamma(x)} by (2.13)",
+                    "reference": f"FP64 oracle evaluated point by point ({acc_s:.1f} s)"}
+        for prec in ("fp64", "fp32"):
+            tdt = torch.float32 if prec == "fp32" else torch.float64
+            plan = V.Plan(c["shape"], c["lo"], c["hi"], Q=c["Q"], M=M, dt=c["dt"], precision=prec,
+                          c0=c["c0"], omega0=c["omega0"])
+            lu = plan.apply(V.VOFL_OP_S1, torch.from_numpy(x_seen).to(dev, tdt)).double().cpu().numpy()
+            lu = lu.reshape(c["shape"])
+            plan.close()
+            got = np.array([lu[j] for j in pts])
+            accuracy[f"max_abs_err_over_max_abs_out_{prec}"] = float(np.max(np.abs(got - ref)) / np.max(np.abs(lu)))
+        if not args.no_extras:
+            workers = max(1, min(16, int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))))
+            O.set_fft_workers(workers)
+            try:
+                t0 = time.perf_counter()
+                O.mterm_apply(x, 1.0 + gamma, c["lo"], c["hi"], M)
+                mt_s = time.perf_counter() - t0
+            finally:
+                O.set_fft_workers(0)
+            cpu_mt = {"value": 1.0 / mt_s, "unit": "applies/s", "cores": workers, "kind": "oracle",
+                      "sample": f"the same apply with scipy.fft on {workers} worker threads: {mt_s:.1f} s"}
+
+    c4x = c5x = None
+    if not args.no_extras:
+        c4x = _c4_short(args, torch, V, dev)
+        c5x = _c5_short(args, torch, V, dev)
+
     prec = args.precision
+    out = {
+        "metric": f"variable-order applies/s at {n}^3, M={M} (two operator applies per TSFP2 step)",
+        "value": head["applies_per_s"],
+        "unit": "applies/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": head["ms_per_step"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32" if prec == "fp32" else "f64",
+        "data": "synthetic",
+        "config": {"workload": WORKLOAD if n == 256 else WORKLOAD.replace("256^3", f"{n}^3"),
+                   "grid": [n, n, n], "M": M, "precision": prec, "solver": "TSFP2 (3.13)"},
+        "gpts_M_per_s": head["gpts_M_per_s"],
+        "apply_only_b2": head["apply_only"].get("b2"),
+        "apply_only": head["apply_only"],
+        "step_time_spread": head["spread"],
+        "roofline": head["roofline"],
+        "whole_step": head["whole_step"],
+        "kernel_ms_per_step": head["kernel_ms_per_step"],
+        "status": head["status"],
+        f"{other}_path": side,
+        "accuracy": accuracy,
+        "cpu_baseline": cpu,
+        "cpu_oracle_multicore": cpu_mt,
+        "c4_batched_shots": c4x,
+        "c5_served_short": c5x,
+    }
+    if side:
+        out["fp32_speedup_over_fp64"] = (side if prec == "fp64" else head)["applies_per_s"] / \
+            (head if prec == "fp64" else side)["applies_per_s"]
+    print(json.dumps(out), flush=True)
+
+
+def _c3_measure(args, torch, V, dev, c, prec, extras):
+    """TSFP2 steps of the 256^3 workload in one precision: K timed steps in one
+    vofl_step call with per-kernel-class HIP events, the dominant kernel's
+    roofline, the whole step's fused bytes over its time, and (extras) the
+    per-step spread and the apply-only rates of 1, 2 and 4 fields."""
+    n, M = c["shape"][0], args.M
     elt = 4 if prec == "fp32" else 8
     tdt = torch.float32 if prec == "fp32" else torch.float64
     plan = V.Plan(c["shape"], c["lo"], c["hi"], Q=c["Q"], M=M, dt=c["dt"], precision=prec,
@@ -154,28 +260,30 @@ def main():
     ktimes = plan.kernel_times()
     plan.set_timing(False)
     status = plan.sync_status()
-    ms_per_step = (t1 - t0) * 1e3 / args.steps
-    applies_per_s = 2.0 * args.steps / (t1 - t0)
+    step_s = (t1 - t0) / args.steps
     N = n ** 3
 
     # dominant kernel class (largest share of device time)
-    dom = max(ktimes.items(), key=lambda kv: kv[1][0])
-    dom_name, (dom_ms, dom_launches) = dom
+    dom_name, (dom_ms, dom_launches) = max(ktimes.items(), key=lambda kv: kv[1][0])
     avg_s = dom_ms / dom_launches / 1e3
     alg = algorithmic_bytes(dom_name, n, M, elt)
     achieved = alg / avg_s / 1e9 if alg > 0 else None
     traffic = None
     tfile = os.path.join(ROOT, "profiles", f"traffic_{dom_name}_256cube_M16_{prec}.json")
-    if os.path.exists(tfile):
+    if n == 256 and M == 16 and os.path.exists(tfile):
         with open(tfile) as f:
             tr = json.load(f)
         if tr.get("source_hash") == kernel_source_hash():
             traffic = tr.get("bytes_per_launch")
+    # whole step: the fused kernels' algorithmic bytes per step over the step time
+    step_classes = ("mid_terms", "c2r0_kick", "mid_dv", "contig_kick")
+    step_bytes = sum(algorithmic_bytes(k, n, M, elt) for k in step_classes)
 
-    # spread of the per-step time (after the timed region): 20 chunks of 10
-    # steps, each bracketed by HIP events on the stream the plan launches on
     spread = None
-    if not args.no_extras:
+    apply_rates = {}
+    if extras:
+        # spread of the per-step time: 20 chunks of 10 steps, each bracketed
+        # by HIP events on the stream the plan launches on
         chunk, nchunks = 10, 20
         evs = [torch.cuda.Event(enable_timing=True) for _ in range(nchunks + 1)]
         evs[0].record()
@@ -187,10 +295,8 @@ def main():
         spread = {"chunk_steps": chunk, "chunks": nchunks, "median_ms_per_step": float(np.median(per_step)),
                   "p99_ms_per_step": float(np.percentile(per_step, 99)), "min_ms_per_step": per_step[0],
                   "max_ms_per_step": per_step[-1]}
-
-    # apply-only throughput for b = 1, 2 (the L1/L2 pair size) and 4 fields, same plan
-    apply_rates = {}
-    for b in ((2,) if args.no_extras else (1, 2, 4)):
+    # apply-only throughput for b = 1, 2 (the L1/L2 pair size) and 4 fields
+    for b in ((1, 2, 4) if extras else (2,)):
         ub = torch.stack([u, v] * 2)[:b].contiguous()
         ob = torch.empty_like(ub)
         for _ in range(3):
@@ -201,97 +307,82 @@ def main():
         for _ in range(reps):
             plan.apply(V.VOFL_OP_S1, ub, ob)
         torch.cuda.synchronize()
-        apply_rates[b] = b / ((time.perf_counter() - t0) / reps)
+        r = b / ((time.perf_counter() - t0) / reps)
+        apply_rates[f"b{b}"] = {"applies_per_s": r, "gpts_M_per_s": N * M * r / 1e9}
         del ub, ob
-    apply_rate = apply_rates[2]
-
-    # comparator: the plain FP64 path (FP64 plan, same workload, eager steps)
-    fp64_cmp = None
-    if not args.no_extras and prec == "fp32":
-        p64 = V.Plan(c["shape"], c["lo"], c["hi"], Q=c["Q"], M=M, dt=c["dt"], precision="fp64",
-                     c0=c["c0"], omega0=c["omega0"])
-        u64 = torch.from_numpy(c["u0"]).to(dev, torch.float64)
-        v64 = torch.from_numpy(c["v0"]).to(dev, torch.float64)
-        p64.step(u64, v64, 2)
-        torch.cuda.synchronize()
-        k64 = 10
-        t0 = time.perf_counter()
-        p64.step(u64, v64, k64)
-        torch.cuda.synchronize()
-        s64 = (time.perf_counter() - t0) / k64
-        fp64_cmp = {"ms_per_step": s64 * 1e3, "applies_per_s": 2.0 / s64, "steps": k64, "status": p64.sync_status()}
-        del p64, u64, v64
-
-    cpu = None
-    cpu_mt = None
-    accuracy = None
-    if not args.no_cpu:
-        import oracle as O
-        gamma = O.gamma_from_Q(c["Q"])
-        x = c["u0"]
-        t0 = time.perf_counter()
-        O.mterm_apply(x, 1.0 + gamma, c["lo"], c["hi"], M)
-        cpu_s = time.perf_counter() - t0
-        cpu = {"value": 1.0 / cpu_s, "unit": "applies/s", "cores": 1, "kind": "oracle",
-               "sample": f"one oracle apply (2.13) of L1 on the {n}^3 M={M} field, FP64 numpy "
-                         f"(pocketfft, single thread): {cpu_s:.1f} s"}
-        # accuracy of the benchmarked plan: L1 of the workload's initial field
-        # (as the plan sees it) against the FP64 oracle at sampled points
-        x_seen = c["u0"].astype(np.float32).astype(np.float64) if prec == "fp32" else c["u0"]
-        u_in = torch.from_numpy(c["u0"]).to(dev, tdt)
-        lu = plan.apply(V.VOFL_OP_S1, u_in).double().cpu().numpy().reshape(c["shape"])
-        rng = np.random.default_rng(np.random.SeedSequence(13049 + 3, spawn_key=(95,)))
-        pts = [tuple(n // 2 for n in c["shape"])] + [tuple(int(rng.integers(k)) for k in c["shape"]) for _ in range(5)]
-        t0 = time.perf_counter()
-        ref = O.mterm_apply_at(x_seen, 1.0 + gamma, c["lo"], c["hi"], M, pts)
-        acc_s = time.perf_counter() - t0
-        got = np.array([lu[j] for j in pts])
-        accuracy = {"max_abs_err_over_max_abs_out": float(np.max(np.abs(got - ref)) / np.max(np.abs(lu))),
-                    "points": len(pts), "operator": "L1 = (-Lap)^{1+gamma(x)} by (2.13)",
-                    "reference": f"FP64 oracle evaluated point by point ({acc_s:.1f} s)"}
-        if not args.no_extras:
-            workers = max(1, min(16, int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))))
-            O.set_fft_workers(workers)
-            try:
-                t0 = time.perf_counter()
-                O.mterm_apply(x, 1.0 + gamma, c["lo"], c["hi"], M)
-                mt_s = time.perf_counter() - t0
-            finally:
-                O.set_fft_workers(0)
-            cpu_mt = {"value": 1.0 / mt_s, "unit": "applies/s", "cores": workers, "kind": "oracle",
-                      "sample": f"the same apply with scipy.fft on {workers} worker threads: {mt_s:.1f} s"}
-
-    out = {
-        "metric": "variable-order applies/s at 256^3, M=16 (two operator applies per TSFP2 step)",
-        "value": applies_per_s,
-        "unit": "applies/s",
-        "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
-        "ms_per_step": ms_per_step,
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": "f32" if prec == "fp32" else "f64",
-        "data": "synthetic",
-        "config": {"workload": WORKLOAD if n == 256 else WORKLOAD.replace("256^3", f"{n}^3"),
-                   "grid": [n, n, n], "M": M, "precision": prec, "solver": "TSFP2 (3.13)"},
-        "gpts_M_per_s": N * M * applies_per_s / 1e9,
-        "apply_only_b2": {"applies_per_s": apply_rate, "gpts_M_per_s": N * M * apply_rate / 1e9},
-        "apply_only": {f"b{b}": {"applies_per_s": r, "gpts_M_per_s": N * M * r / 1e9} for b, r in apply_rates.items()},
-        "step_time_spread": spread,
+    plan.close()
+    return {
+        "precision": prec,
+        "applies_per_s": 2.0 / step_s,
+        "ms_per_step": step_s * 1e3,
+        "gpts_M_per_s": N * M * 2.0 / step_s / 1e9,
+        "status": status,
         "roofline": {"bound": "hbm", "kernel": dom_name, "achieved": achieved, "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": (achieved / HBM_PEAK_GBS) if achieved else None,
-                     "traffic": traffic, "alg_bytes_per_launch": alg,
-                     "avg_launch_ms": avg_s * 1e3},
+                     "traffic": traffic, "alg_bytes_per_launch": alg, "avg_launch_ms": avg_s * 1e3},
+        "whole_step": {"alg_bytes_per_step": step_bytes, "achieved_GBps": step_bytes / step_s / 1e9,
+                       "frac": step_bytes / step_s / 1e9 / HBM_PEAK_GBS,
+                       "note": "sum of the fused kernels' algorithmic bytes over the step time"},
         "kernel_ms_per_step": {k: ms / args.steps for k, (ms, _) in ktimes.items()},
-        "status": status,
-        "fp64_path": fp64_cmp,
-        "accuracy": accuracy,
-        "cpu_baseline": cpu,
-        "cpu_oracle_multicore": cpu_mt,
+        "kernel_GBps": {k: algorithmic_bytes(k, n, M, elt) / (ms / nl / 1e3) / 1e9
+                        for k, (ms, nl) in ktimes.items() if algorithmic_bytes(k, n, M, elt) > 0},
+        "apply_only": apply_rates,
+        "spread": spread,
     }
-    print(json.dumps(out), flush=True)
+
+
+def _c4_short(args, torch, V, dev):
+    """Batched shots (64 x 512^2 with a shared Q + 16 x 768^2 with their own Q,
+    M = 12, FP32), default kernel variants: ms per whole-batch step, eager
+    vofl_step_batch, 10 timed steps after 2 warm-up steps."""
+    from workloads import c4_inputs
+    c = c4_inputs()
+    plans, us, vs, nshots, Ntot = [], [], [], 0, 0
+    for big in (False, True):
+        shots = [sh for sh in c["shots"] if (sh["shape"][0] == 768) == big]
+        Q = np.stack([sh["Q"] for sh in shots]) if big else shots[0]["Q"]
+        plans.append(V.Plan(shots[0]["shape"], c["lo"], c["hi"], Q=Q, M=c["M"], dt=c["dt"], precision="fp32",
+                            c0=c["c0"], omega0=c["omega0"], batch=len(shots), coef_per_solve=big))
+        us.append(torch.from_numpy(np.stack([sh["u0"] for sh in shots])).to(dev, torch.float32))
+        vs.append(torch.zeros_like(us[-1]))
+        nshots += len(shots)
+        Ntot += len(shots) * int(np.prod(shots[0]["shape"]))
+    hs = [p.handle for p in plans]
+
+    def run(k):
+        V.vofl_step_batch(hs, [u.data_ptr() for u in us], [v.data_ptr() for v in vs], [k] * len(hs),
+                          torch.cuda.current_stream().cuda_stream)
+    run(2)
+    torch.cuda.synchronize()
+    k = 10
+    t0 = time.perf_counter()
+    run(k)
+    torch.cuda.synchronize()
+    step_s = (time.perf_counter() - t0) / k
+    status = [p.sync_status() for p in plans]
+    for p in plans:
+        p.close()
+    return {"ms_per_batch_step": step_s * 1e3, "shot_steps_per_s": nshots / step_s,
+            "gpts_M_per_s": Ntot * c["M"] * 2 / step_s / 1e9, "steps": k, "status": status,
+            "workload": "64 x 512^2 (shared GRF Q) + 16 x 768^2 (own GRF Q), M=12, FP32, dt=5e-4; "
+                        "eager vofl_step_batch, default kernel variants"}
+
+
+def _c5_short(args, torch, V, dev, count=30, step_scale=0.1):
+    """A short request stream: the first `count` requests of the Poisson trace
+    (mean 200 req/s) with their step counts scaled by step_scale, served with
+    continuous batching, then by the plain FP64 path one request at a time."""
+    from paper_2311_13049_amd import serve as S
+    from workloads import c5_requests
+    reqs = S.requests_from_stream(c5_requests(count=count), step_scale=step_scale)
+    _, served = S.Server(slots=16, graphs=True).run(reqs, realtime=True)
+    _, plain = S.Server(slots=1, chunk=0, graphs=False, precision="fp64").run(reqs, realtime=True)
+    keys = ("requests", "completed", "p50_latency_s", "p99_latency_s", "requests_per_s", "gpts_M_steps_per_s",
+            "mean_queue_s", "mean_service_s")
+    return {"requests": count, "step_scale": step_scale,
+            "served": {k: served.get(k) for k in keys},
+            "plain_fp64_single_solve": {k: plain.get(k) for k in keys},
+            "workload": f"first {count} requests of the c5 Poisson stream (200 req/s), steps x {step_scale}"}
 
 
 def _fork_join(torch, streams, fns):
@@ -607,6 +698,8 @@ def bench_c5(args, torch, V, dev):
     served, st_served = S.Server(slots=16, graphs=True).run(reqs, realtime=True)
     print(json.dumps({"served": st_served}), flush=True)
     plain, st_plain = S.Server(slots=1, chunk=0, graphs=False, precision="fp64").run(reqs, realtime=True)
+    print(json.dumps({"plain_fp64": st_plain}), flush=True)
+    _, st_plain32 = S.Server(slots=1, chunk=0, graphs=False, precision="fp32").run(reqs, realtime=True)
     span = max(r.arrival for r in reqs) - min(r.arrival for r in reqs)
     demand = sum(r.service for r in plain.values() if r.status == "ok")
     work = sum(r.N * r.M * r.steps for r in reqs)
@@ -618,6 +711,7 @@ def bench_c5(args, torch, V, dev):
                                "256^3, M in {8,16}, steps U{100..2000}, FP32 or FP64, GRF Q"},
         "served": st_served,
         "plain_fp64_single_solve": st_plain,
+        "plain_fp32_single_solve": st_plain32,
         "offered_load": demand / max(span, 1e-9),
         "offered_load_note": "GPU-seconds of the plain path per second of trace",
         "work_gpts_M_steps": work / 1e9,
