@@ -259,6 +259,44 @@ struct LdsPencil {
     __device__ __forceinline__ cpx<T>& operator[](int i) const { return base[i + (i >> 3)]; }
     static constexpr int footprint(int N) { return N + N / 8; }
 };
+// Swizzled pencil layout: element i at base[i ^ x(i)], x(i) built from
+// single index bits above the low five XORed into them, chosen per length,
+// elements per thread and element size so that the exchanges of the
+// Stockham stages (blocked writes, strided writes, cyclic reads) reach
+// distinct LDS banks in every 256-byte group of lanes. Lengths without a
+// table entry use the one-pad-per-8 layout.
+struct SwzMasks {
+    int src[5];  // source bit for low bit b, or -1
+};
+constexpr SwzMasks pencil_swizzle(int N, int E, int bytes) {
+    if (bytes == 8) {
+        if ((N == 256 || N == 512) && E == 8) return {{5, 6, 7, 6, 7}};
+        if ((N == 256 || N == 1024) && E == 4) return {{5, 6, 5, 6, 6}};
+    } else if (bytes == 16) {
+        if ((N == 128 || N == 256 || N == 512) && E == 8) return {{4, 5, 6, 6, -1}};
+        if ((N == 256 || N == 1024) && E == 4) return {{4, 5, 4, 5, -1}};
+    }
+    return {{-1, -1, -1, -1, -1}};
+}
+template <typename T, int N, int E>
+struct LdsPencilX {
+    static constexpr SwzMasks S = pencil_swizzle(N, E, int(sizeof(cpx<T>)));
+    static constexpr bool SWZ = S.src[0] >= 0;
+    cpx<T>* base;
+    __device__ __forceinline__ static int map(int i) {
+        if constexpr (!SWZ) {
+            return i + (i >> 3);
+        } else {
+            int x = i;
+#pragma unroll
+            for (int b = 0; b < 5; ++b)
+                if (S.src[b] >= 0) x ^= ((i >> S.src[b]) & 1) << b;
+            return x;
+        }
+    }
+    __device__ __forceinline__ cpx<T>& operator[](int i) const { return base[map(i)]; }
+    static constexpr int footprint(int n) { return SWZ ? n : n + n / 8; }
+};
 template <typename T, int W>
 struct LdsColumn {
     cpx<T>* base;  // already offset by the column index

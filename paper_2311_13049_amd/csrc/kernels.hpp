@@ -198,8 +198,12 @@ struct ContigArgs {
 template <typename T, typename TI, int N, int E, int P, bool NT = false>
 __global__ __launch_bounds__(P*(N / E)) void k_contig(ContigArgs<T, TI> a) {
     constexpr int TP = N / E;
-    constexpr int FPI = LdsPencil<TI>::footprint(N);
-    constexpr int FP = LdsPencil<T>::footprint(N);
+    // swizzled pencils: the exchanges of every stage are free of LDS bank
+    // conflicts (one-pad-per-8 layout where the length has no table entry)
+    using LPI = LdsPencilX<TI, N, E>;
+    using LPT = LdsPencilX<T, N, E>;
+    constexpr int FPI = LPI::footprint(N);
+    constexpr int FP = LPT::footprint(N);
     __shared__ cpx<TI> lds_raw[P * FPI];  // holds P pencils of TI (>= size of T)
     __shared__ cpx<TI> twi_s[N];
     __shared__ cpx<T> tw_s[N];
@@ -211,8 +215,8 @@ __global__ __launch_bounds__(P*(N / E)) void k_contig(ContigArgs<T, TI> a) {
     const int bi = blockIdx.y;
     const bool active = p < a.npencils;
     const int pc = active ? p : 0;
-    const LdsPencil<TI> ldsi{lds_raw + lp * FPI};
-    const LdsPencil<T> lds{reinterpret_cast<cpx<T>*>(lds_raw) + lp * FP};
+    const LPI ldsi{lds_raw + lp * FPI};
+    const LPT lds{reinterpret_cast<cpx<T>*>(lds_raw) + lp * FP};
     const int k0 = pc / a.n1;
     const int k1 = pc % a.n1;
     const double m2base = a.mu2_0[k0] + (a.mu2_1 ? a.mu2_1[k1] : 0.0);
@@ -228,8 +232,8 @@ __global__ __launch_bounds__(P*(N / E)) void k_contig(ContigArgs<T, TI> a) {
     cpx<T> twr[TWC];
     if constexpr (TWREG) load_twiddles<T, N, E, TWC>(twr, t, tw_s);
     auto inv_fft = [&](cpx<T> (&x)[E]) __attribute__((always_inline)) {
-        if constexpr (TWREG) fft_pencil_r<T, N, E, +1, LdsPencil<T>, WV, TWC>(x, t, lds, twr);
-        else fft_pencil<T, N, E, +1, LdsPencil<T>, WV>(x, t, lds, tw_s);
+        if constexpr (TWREG) fft_pencil_r<T, N, E, +1, LPT, WV, TWC>(x, t, lds, twr);
+        else fft_pencil<T, N, E, +1, LPT, WV>(x, t, lds, tw_s);
     };
 
     cpx<double> uh[E], vh[E];
@@ -246,7 +250,7 @@ __global__ __launch_bounds__(P*(N / E)) void k_contig(ContigArgs<T, TI> a) {
         const cpx<TI>* src = a.in + (long long)bi * a.in_istride + pen;
 #pragma unroll
         for (int e = 0; e < E; ++e) d[e] = src[t + TP * e];
-        fft_pencil<TI, N, E, -1, LdsPencil<TI>, WV>(d, t, ldsi, twi_s);
+        fft_pencil<TI, N, E, -1, LPI, WV>(d, t, ldsi, twi_s);
         const cpx<double>* Us = a.U + (long long)bi * a.H + pen;
         const cpx<double>* Vs = a.V + (long long)bi * a.H + pen;
         const double s = a.dt * a.invN;
@@ -262,7 +266,7 @@ __global__ __launch_bounds__(P*(N / E)) void k_contig(ContigArgs<T, TI> a) {
             const cpx<TI>* src = a.in + (long long)bi * a.in_istride + (long long)f * a.in_fstride + pen;
 #pragma unroll
             for (int e = 0; e < E; ++e) d[e] = src[t + TP * e];
-            fft_pencil<TI, N, E, -1, LdsPencil<TI>, WV>(d, t, ldsi, twi_s);
+            fft_pencil<TI, N, E, -1, LPI, WV>(d, t, ldsi, twi_s);
 #pragma unroll
             for (int e = 0; e < E; ++e) {
                 const cpx<double> z = {double(d[e].x) * a.invN, double(d[e].y) * a.invN};

@@ -8,13 +8,15 @@
 
 namespace vofl {
 
-// Elements per thread of each kernel class for a transform length N. Lengths
+// Elements per thread of each kernel class for a transform length N (the
+// last-axis kernel uses 4 at 256: one 64-thread pencil per wavefront, fewer
+// registers per thread than 8, so more wavefronts per SIMD). Lengths
 // with a factor 3 (3 * 2^k) use 12 elements per thread (radix 4 stages and
 // one radix-3 stage); lengths with a factor 5 (1000 = 2^3 5^3) use 10
 // (radix-5 and radix-2 stages, 100 threads per pencil).
 constexpr bool has3(int N) { return N % 3 == 0; }
 constexpr bool has5(int N) { return N % 5 == 0; }
-constexpr int e_contig(int N) { return has5(N) ? 10 : has3(N) ? 12 : (N < 8 ? N : (N >= 1024 ? 4 : 8)); }
+constexpr int e_contig(int N) { return has5(N) ? 10 : has3(N) ? 12 : (N < 8 ? N : ((N >= 1024 || N == 256) ? 4 : 8)); }
 constexpr int e_mid(int N) { return has5(N) ? 10 : has3(N) ? 12 : (N < 16 ? N : 16); }
 constexpr int e_r2c0(int N) { return has5(N) ? 10 : has3(N) ? 12 : (N < 16 ? N : 16); }
 constexpr int e_c2r0(int N) { return has5(N) ? 10 : has3(N) ? 12 : (N < 8 ? N : 8); }
@@ -32,6 +34,7 @@ struct Launch {
     static int tile_w(int N);
     static int c2r_w(int N);
     static int c2r_tile(int N, int variant);
+    static int c2r_default(int N);
     // whether an axis-0 variant has its own kernel for length N (else it falls back to 0)
     static bool c2r_variant_exists(int N, int variant);
     template <typename TI>

@@ -199,7 +199,9 @@ hipError_t c2r0_mode(const C2RArgs<T>& a, int items, hipStream_t s) {
 }
 
 // Bytes of term slots one k_c2r0 launch reads: above the 256 MB last-level
-// cache the paired default streams them with the non-temporal policy.
+// cache the paired default streams them with the non-temporal policy (only
+// on tiles whose rows fill a 128-byte line: a half line loaded
+// non-temporally is fetched again for the neighbouring tile).
 template <typename T>
 bool c2r0_streams(const C2RArgs<T>& a, int items) {
     const long long slots = a.mode == C2R_EXPORT ? 2 : a.mode == C2R_APPLY ? a.M + 1
@@ -240,7 +242,10 @@ hipError_t Launch<T>::c2r0(int N, const C2RArgs<T>& a, int items, hipStream_t s,
         if constexpr (E % 2 == 0)                                                       \
             if (variant == 14) return c2r0_mode<T, n, E, W, 1, 1, false, true>(a, items, s); \
         if constexpr (paired_ok<n, E, W2>() && W2 != W)                                  \
-            if (variant == 13) return c2r0_mode<T, n, E, W2, 1, 1, true>(a, items, s);   \
+            if (variant == 13)                                                          \
+                return (c2r0_streams(a, items) && W2 * int(sizeof(cpx<T>)) >= 128)        \
+                           ? c2r0_mode<T, n, E, W2, 1, 1, true, false, true>(a, items, s) \
+                           : c2r0_mode<T, n, E, W2, 1, 1, true>(a, items, s);            \
         if constexpr (paired_ok<n, E, W>()) {                                           \
             if (variant == 11)                                                          \
                 return c2r0_streams(a, items) ? c2r0_mode<T, n, E, W, 1, 1, true, false, true>(a, items, s) \
@@ -279,6 +284,28 @@ bool Launch<T>::c2r_variant_exists(int N, int variant) {
         VOFL_MULTI_SIZES(C_)
 #undef C_
         default: return false;
+    }
+}
+
+// Default axis-0 variant: each stored row loaded once. The paired layout on
+// the narrowest tile whose rows still fill a 128-byte line (13: half-width
+// tiles, the FP64 case; 11: full width), else the LDS-staged loads (14),
+// else direct loads (0). Narrower tiles give more workgroups per CU at the
+// same register count; rows shorter than a line would be fetched twice.
+template <typename T>
+int Launch<T>::c2r_default(int N) {
+    switch (N) {
+#define C_(n)                                                                           \
+    case n: {                                                                           \
+        constexpr int W = c2r_width<T, n>(), E = e_c2r0(n);                             \
+        constexpr int W2 = (W >= 8) ? W / 2 : W;                                        \
+        if (W2 != W && paired_ok<n, E, W2>() && W2 * int(sizeof(cpx<T>)) >= 128) return 13; \
+        if (paired_ok<n, E, W>()) return 11;                                            \
+        return (E % 2 == 0) ? 14 : 0;                                                   \
+    }
+        VOFL_MULTI_SIZES(C_)
+#undef C_
+        default: return 0;
     }
 }
 

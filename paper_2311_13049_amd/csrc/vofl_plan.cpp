@@ -1313,15 +1313,10 @@ int vofl_plan(const vofl_desc* d, void* stream, vofl_plan_t* out) {
         p->w1 = 1.0 / (2.0 - c);
         p->w0 = -c / (2.0 - c);
     }
-    // default axis-0 kernel: each stored row loaded once, by the paired
-    // layout where the length allows it, else through the LDS stage
-    if (g.ndim >= 2) {
-        auto exists = [&](int v) {
-            return (d->precision == VOFL_FP32) ? Launch<float>::c2r_variant_exists(g.n[0], v)
-                                               : Launch<double>::c2r_variant_exists(g.n[0], v);
-        };
-        p->c2r_variant = exists(11) ? 11 : exists(14) ? 14 : 0;
-    }
+    // default axis-0 kernel: each stored row loaded once (see c2r_default)
+    if (g.ndim >= 2)
+        p->c2r_variant = (d->precision == VOFL_FP32) ? Launch<float>::c2r_default(g.n[0])
+                                                     : Launch<double>::c2r_default(g.n[0]);
     if (const char* ev = std::getenv("VOFL_C2R_VARIANT")) p->c2r_variant = std::atoi(ev);
     if (const char* ev = std::getenv("VOFL_MID_VARIANT")) {
         // only 0, 1, 2 exist; the launcher's grid and kernel tile must agree
