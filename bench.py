@@ -438,12 +438,38 @@ def bench_c4(args, torch, V, dev):
         fn(steps)
         torch.cuda.synchronize()
         timings[name] = time.perf_counter() - t0
+    # each group alone on the current stream: eager steps against graph
+    # replays of the same steps (the graph's own cost per launch)
+    per_group = {}
+    cur = torch.cuda.current_stream().cuda_stream
+    for g in groups:
+        h, up, vp = g["plan"].handle, g["u"].data_ptr(), g["v"].data_ptr()
+        res = {}
+        for mode in ("eager", "graph"):
+            fn = (lambda k: V.vofl_step(h, up, vp, k, cur)) if mode == "eager" else \
+                 (lambda k: V.vofl_step_graph(h, up, vp, k, cur))
+            fn(steps)  # warm (and capture)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            fn(steps)
+            torch.cuda.synchronize()
+            res[f"{mode}_ms_per_step"] = (time.perf_counter() - t0) / steps * 1e3
+        per_group[f"{len(g['shots'])} x {g['shots'][0]['shape'][0]}^2"] = res
     status = [g["plan"].sync_status() for g in groups]
     nshots = sum(len(g["shots"]) for g in groups)
     Ntot = sum(len(g["shots"]) * int(np.prod(g["shots"][0]["shape"])) for g in groups)
-    # algorithmic bytes of a step: (2M+3) real-field transforms, each one
-    # read and one write of the field per axis pass (2 passes in 2D)
-    bstep = (2 * c["M"] + 3) * 2 * 2 * Ntot * 4
+    # algorithmic bytes of a step of the fused kernels (2D: the kick's axis-0
+    # pass and the last-axis pass), per shot with H = (n/2+1) n half-spectrum
+    # elements, FP32 complex c = 8 B: c2r0_kick 2(M+1) H c + N (8 + 2*4) + H c,
+    # contig_kick H c + 4*16 H + 2(M+1) H c
+    bstep = 0
+    for g in groups:
+        n0 = g["shots"][0]["shape"][0]
+        Ns, Hs, cb, nterm = n0 * n0, (n0 // 2 + 1) * n0, 8, 2 * (c["M"] + 1)
+        bstep += len(g["shots"]) * (nterm * Hs * cb + Ns * 16 + Hs * cb + Hs * cb + 64 * Hs + nterm * Hs * cb)
+    # the survey's unfused model: (2M+3) real-field transforms, one read and
+    # one write of the field per axis pass (an effective rate, not HBM bytes)
+    bstep_model = (2 * c["M"] + 3) * 2 * 2 * Ntot * 4
 
     # plain FP64 single-solve path: one shot per plan, eager vofl_step,
     # one shot at a time; timed on two shots of each size, scaled to the batch
@@ -475,10 +501,14 @@ def bench_c4(args, torch, V, dev):
         "config": {"workload": "c4 batched shots: 64 x 512^2 on [-32,32)^2 sharing one GRF Q + 16 x 768^2 "
                                "with their own GRF Q, M=12, FP32, dt=5e-4"},
         "ms_per_step_by_mode": {k: t / steps * 1e3 for k, t in timings.items()},
+        "per_group_alone": per_group,
         "applies_per_s": 2 * nshots / step_s,
         "gpts_M_per_s": Ntot * c["M"] * 2 / step_s / 1e9,
         "roofline": {"bound": "hbm", "achieved": bstep / step_s / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": bstep / step_s / 1e9 / HBM_PEAK_GBS, "alg_bytes_per_step": bstep},
+                     "frac": bstep / step_s / 1e9 / HBM_PEAK_GBS, "alg_bytes_per_step": bstep,
+                     "note": "fused kernels' algorithmic bytes of a whole batch step over its time"},
+        "effective_rate_unfused_model": {"bytes_per_step": bstep_model, "GBps": bstep_model / step_s / 1e9,
+                                         "note": "the (2M+3)-transform unfused model; not HBM traffic"},
         "plain_fp64_single_solve": {"ms_per_step_whole_batch": plain_step * 1e3,
                                     "ms_per_shot_step": {k: t * 1e3 for k, t in plain.items()},
                                     "speedup_of_batched": plain_step / step_s,
@@ -692,13 +722,19 @@ def bench_c5(args, torch, V, dev):
     from paper_2311_13049_amd import serve as S
     from workloads import c5_requests
     t0 = time.perf_counter()
-    reqs = S.requests_from_stream(c5_requests(count=args.requests))
+    reqs = S.requests_from_stream(c5_requests(count=args.requests),
+                                  progress=lambda i, n: print(f"c5 inputs {i}/{n}", file=sys.stderr, flush=True))
     gen_s = time.perf_counter() - t0
     print(json.dumps({"c5_inputs_ready_s": gen_s, "requests": len(reqs)}), flush=True)
+    print("c5 serving the trace", file=sys.stderr, flush=True)
     served, st_served = S.Server(slots=16, graphs=True).run(reqs, realtime=True)
     print(json.dumps({"served": st_served}), flush=True)
     plain, st_plain = S.Server(slots=1, chunk=0, graphs=False, precision="fp64").run(reqs, realtime=True)
     print(json.dumps({"plain_fp64": st_plain}), flush=True)
+    print("c5 plain path, each request in its own precision", file=sys.stderr, flush=True)
+    _, st_plain_mix = S.Server(slots=1, chunk=0, graphs=False).run(reqs, realtime=True)
+    print(json.dumps({"plain_mixed": st_plain_mix}), flush=True)
+    print("c5 plain path, all requests in FP32", file=sys.stderr, flush=True)
     _, st_plain32 = S.Server(slots=1, chunk=0, graphs=False, precision="fp32").run(reqs, realtime=True)
     span = max(r.arrival for r in reqs) - min(r.arrival for r in reqs)
     demand = sum(r.service for r in plain.values() if r.status == "ok")
@@ -711,11 +747,16 @@ def bench_c5(args, torch, V, dev):
                                "256^3, M in {8,16}, steps U{100..2000}, FP32 or FP64, GRF Q"},
         "served": st_served,
         "plain_fp64_single_solve": st_plain,
+        "plain_single_solve_request_precision": st_plain_mix,
         "plain_fp32_single_solve": st_plain32,
+        "note": "served and plain_single_solve_request_precision run each request in its own precision "
+                "(half FP32, half FP64); the two other plain runs force one precision on every request",
         "offered_load": demand / max(span, 1e-9),
         "offered_load_note": "GPU-seconds of the plain path per second of trace",
         "work_gpts_M_steps": work / 1e9,
         "speedup_requests_per_s": (st_served.get("requests_per_s") or 0) / max(st_plain.get("requests_per_s") or 1e-30, 1e-30),
+        "speedup_over_plain_same_precisions": (st_served.get("requests_per_s") or 0) /
+                                              max(st_plain_mix.get("requests_per_s") or 1e-30, 1e-30),
         "p99_latency_ratio_plain_over_served": (st_plain.get("p99_latency_s") or 0) / max(st_served.get("p99_latency_s") or 1e-30, 1e-30),
     }
     print(json.dumps(out), flush=True)

@@ -405,12 +405,16 @@ def summarize(results, requests) -> dict:
     return out
 
 
-def requests_from_stream(stream, step_scale: float = 1.0) -> list:
+def requests_from_stream(stream, step_scale: float = 1.0, progress=None) -> list:
     """Turn request records (index, arrival, shape, M, steps, precision, seed)
-    into Requests with their seeded inputs (box, dt, Q field, pulse)."""
+    into Requests with their seeded inputs (box, dt, Q field, pulse).
+    progress: optional callable(done, total) called every 20 requests."""
     from workloads import c5_request_inputs
     out = []
-    for rec in stream:
+    stream = list(stream)
+    for i, rec in enumerate(stream):
+        if progress and i % 20 == 0:
+            progress(i, len(stream))
         x = c5_request_inputs(rec)
         steps = max(1, int(round(rec["steps"] * step_scale)))
         out.append(Request(index=rec["index"], arrival=rec["arrival"], shape=x["shape"], M=rec["M"],
