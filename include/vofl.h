@@ -237,6 +237,25 @@ int vofl_step_graph(vofl_plan_t plan, void* u, void* v, int nsteps, void* stream
 int vofl_step_batch(vofl_plan_t* plans, void** u, void** v, const int* nsteps,
                     int count, void* stream);
 
+/* Allocation-free apply, for callers that cannot allocate device memory
+ * (code under HIP graph capture, serving loops that forbid allocation; no
+ * plan is needed). Computes the M-term operator (2.13) of order s(x) on a 1D
+ * periodic grid of n points on [lo, hi) for nfields fields, as vofl_apply
+ * does for a plan of that grid, order field and M:
+ *   out_f = sum_{m=0..M} delta^m IDFT[l_m |mu|^{2 s0} DFT(u_f)/N],
+ * s0 the grid mean of s, delta = s - s0 (for (1.1) pass s = 1 + gamma or
+ * 1/2 + gamma). s: device, n FP64 values in (0, 2]; u, out: device,
+ * nfields * n values in the given precision, out != u. n must be a compiled
+ * 1D length (8 ... 4096) whose tables fit the library's 256 KiB static
+ * scratch array (every compiled length does), else VOFL_ERR_UNSUPPORTED or
+ * VOFL_ERR_INVALID. The call allocates nothing: the grid mean, delta, the
+ * symbol and twiddle tables are formed on the device in the static array
+ * (one per GPU, kept until the process ends, reused by every call), so
+ * calls that overlap on one GPU race; order them on one stream.
+ * Asynchronous on stream. */
+int vofl_apply_noalloc(int n, double lo, double hi, const double* s, int M, int precision,
+                       const void* u, void* out, int nfields, void* stream);
+
 /* Synchronize stream, then report VOFL_ERR_UNSTABLE if the plan's
  * non-finite flag is set (the flag is cleared by the read). */
 int vofl_sync_status(vofl_plan_t plan, void* stream);

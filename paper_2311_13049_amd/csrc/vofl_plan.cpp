@@ -1101,6 +1101,11 @@ int run_end_any(vofl_plan_s* p, void* u, void* v, int phase, hipStream_t s) {
 
 }  // namespace
 
+namespace vofl {
+// error reporting for the allocation-free entry point (noalloc.hip)
+int noalloc_fail(int code, const char* msg) { return fail(code, "%s", msg); }
+}  // namespace vofl
+
 // ---------------------------------------------------------------------------
 // autotuning of the axis-0 and middle-axis kernel variants
 // ---------------------------------------------------------------------------

@@ -34,7 +34,7 @@ ABI_FUNCTIONS = (
     "vofl_plan", "vofl_plan_footprint", "vofl_apply", "vofl_step", "vofl_step_graph", "vofl_solve",
     "vofl_step_begin", "vofl_step_advance", "vofl_step_end", "vofl_lffp_start", "vofl_lffp_step",
     "vofl_cnfp_step", "vofl_step_batch", "vofl_sync_status", "vofl_set_timing", "vofl_kernel_times",
-    "vofl_plan_info", "vofl_destroy", "vofl_last_error", "vofl_version",
+    "vofl_plan_info", "vofl_destroy", "vofl_last_error", "vofl_version", "vofl_apply_noalloc",
 )
 
 _c_double_p = ctypes.POINTER(ctypes.c_double)
@@ -107,13 +107,15 @@ def load_library():
                                       ctypes.POINTER(ctypes.c_longlong), ctypes.c_int]
     lib.vofl_plan_info.argtypes = [vp, _c_double_p, ctypes.c_int]
     lib.vofl_destroy.argtypes = [vp]
+    lib.vofl_apply_noalloc.argtypes = [ctypes.c_int, ctypes.c_double, ctypes.c_double, vp, ctypes.c_int,
+                                       ctypes.c_int, vp, vp, ctypes.c_int, vp]
     lib.vofl_last_error.restype = ctypes.c_char_p
     lib.vofl_version.restype = ctypes.c_char_p
     for name in ("vofl_plan", "vofl_plan_footprint", "vofl_apply", "vofl_step", "vofl_step_graph", "vofl_solve",
                  "vofl_step_begin", "vofl_step_advance", "vofl_step_end", "vofl_lffp_start", "vofl_lffp_step",
                  "vofl_cnfp_step",
                  "vofl_step_batch", "vofl_sync_status", "vofl_set_timing", "vofl_kernel_times",
-                 "vofl_plan_info", "vofl_destroy"):
+                 "vofl_plan_info", "vofl_destroy", "vofl_apply_noalloc"):
         getattr(lib, name).restype = ctypes.c_int
     _lib = lib
     return lib
@@ -193,6 +195,13 @@ def vofl_step(plan: int, u_ptr: int, v_ptr: int, nsteps: int, stream=0) -> None:
 def vofl_step_graph(plan: int, u_ptr: int, v_ptr: int, nsteps: int, stream=0) -> None:
     _check(load_library().vofl_step_graph(ctypes.c_void_p(plan), ctypes.c_void_p(u_ptr),
                                           ctypes.c_void_p(v_ptr), nsteps, ctypes.c_void_p(stream)))
+
+
+def vofl_apply_noalloc(n: int, lo: float, hi: float, s_ptr: int, M: int, precision: int, u_ptr: int,
+                       out_ptr: int, nfields: int, stream=0) -> None:
+    _check(load_library().vofl_apply_noalloc(int(n), float(lo), float(hi), ctypes.c_void_p(s_ptr), int(M),
+                                             int(precision), ctypes.c_void_p(u_ptr), ctypes.c_void_p(out_ptr),
+                                             int(nfields), ctypes.c_void_p(stream)))
 
 
 def vofl_step_begin(plan: int, u_ptr: int, v_ptr: int, stream=0) -> None:
