@@ -514,7 +514,8 @@ def bench_c4(args, torch, V, dev):
                                     "speedup_of_batched": plain_step / step_s,
                                     "sample": "2 shots of each size, solved one at a time, scaled to 64 + 16"},
         "plan_build_s": [g["plan_s"] for g in groups],
-        "tuned_variants": [{"c2r": g["info"]["c2r_variant"], "mid": g["info"]["mid_variant"]} for g in groups],
+        "tuned_variants": [{"c2r": g["info"]["c2r_variant"], "mid": g["info"]["mid_variant"],
+                            "last_axis_schedule": g["info"]["contig_variant"]} for g in groups],
         "status": status,
     }
     print(json.dumps(out), flush=True)

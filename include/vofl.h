@@ -83,8 +83,11 @@ typedef struct vofl_desc {
                             all solves; 1: batch fields (batch * N values), one per solve */
     size_t hbm_budget;   /* bytes of device memory the plan may take; 0 = no limit     */
     int tune_steps;      /* 0: default kernel variants; > 0: vofl_plan times each
-                            candidate tile/radix variant over this many steps on
-                            temporary buffers and keeps the fastest (cached in the
+                            candidate over this many steps on temporary buffers and
+                            keeps the fastest: the axis-0 kernel variants x the
+                            middle-axis tile widths, then the last-axis radix
+                            schedule (4 or 8 elements per thread for power-of-two
+                            lengths 64..1024) with the best pair (cached in the
                             file named by VOFL_TUNE_CACHE, when set)                 */
     int order;           /* time splitting of vofl_step: 0 or 2: TSFP2 (3.13); 4: the
                             higher-order splitting named after (3.13), built as the
@@ -113,7 +116,8 @@ typedef struct vofl_plan_s* vofl_plan_t;
  * retained. The environment variables VOFL_C2R_VARIANT (axis-0 kernel: 0, 2,
  * 5, 6, 11, 12, 13, 14) and VOFL_MID_VARIANT (middle-axis tile: 0, 1, 2)
  * force a kernel variant instead of the default (a variant without a kernel
- * for the plan's length runs as variant 0); results agree to rounding. */
+ * for the plan's length runs as variant 0) and VOFL_CONTIG_VARIANT (last-axis
+ * radix schedule: 0, 1); results agree to rounding. */
 int vofl_plan(const vofl_desc* desc, void* stream, vofl_plan_t* out);
 
 /* Device bytes a plan for desc would allocate (same validation as vofl_plan,
@@ -270,7 +274,9 @@ int vofl_kernel_times(vofl_plan_t plan, const char** names, double* ms,
 
 /* Plan scalars (FP64): out[0] = gbar (or s0), out[1] = kappa0, out[2] = beta0,
  * out[3] = N, out[4] = device bytes held, out[5] = axis-0 kernel variant,
- * out[6] = middle-axis kernel variant. Returns VOFL_OK. */
+ * out[6] = middle-axis kernel variant, out[7] = last-axis schedule (0: the
+ * default elements per thread, 1: the alternative). Writes min(cap, 8)
+ * values. Returns VOFL_OK. */
 int vofl_plan_info(vofl_plan_t plan, double* out, int cap);
 
 int vofl_destroy(vofl_plan_t plan);

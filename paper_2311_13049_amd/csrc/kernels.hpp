@@ -225,14 +225,18 @@ __global__ __launch_bounds__(P*(N / E)) void k_contig(ContigArgs<T, TI> a) {
     // a pencil's TP threads are consecutive and TP divides 64: every
     // transform stays inside one wavefront
     constexpr bool WV = (TP <= 64) && (64 % TP == 0);
-    // the inverse transforms of the terms use this thread's twiddles from
-    // registers (one table read per kernel instead of one per transform)
-    constexpr bool TWREG = E <= 8 && tw_count(N, E) > 0 && tw_count(N, E) <= 16;
-    constexpr int TWC = TWREG ? tw_count(N, E) : 1;
-    cpx<T> twr[TWC];
-    if constexpr (TWREG) load_twiddles<T, N, E, TWC>(twr, t, tw_s);
+    // the inverse transforms of the terms read this thread's twiddles from a
+    // per-position LDS table (conflict-free, consecutive lanes read
+    // consecutive entries) instead of the strided length-N table
+    constexpr int TWC = tw_count(N, E);
+    constexpr bool TWT = TWC > 0;
+    __shared__ cpx<T> twt_s[TWT ? TWC * TP : 1];
+    if constexpr (TWT) {
+        if (lp == 0) thread_twiddles_at<T, N, E, 1>(twt_s, t, tw_s);
+        __syncthreads();
+    }
     auto inv_fft = [&](cpx<T> (&x)[E]) __attribute__((always_inline)) {
-        if constexpr (TWREG) fft_pencil_r<T, N, E, +1, LPT, WV, TWC>(x, t, lds, twr);
+        if constexpr (TWT) fft_pencil_t<T, N, E, +1, LPT, WV>(x, t, lds, twt_s);
         else fft_pencil<T, N, E, +1, LPT, WV>(x, t, lds, tw_s);
     };
 

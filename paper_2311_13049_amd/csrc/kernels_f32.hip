@@ -5,6 +5,6 @@
 
 namespace vofl {
 template struct Launch<float>;
-template hipError_t Launch<float>::contig<float>(int, const ContigArgs<float, float>&, int, hipStream_t);
-template hipError_t Launch<float>::contig<double>(int, const ContigArgs<float, double>&, int, hipStream_t);
+template hipError_t Launch<float>::contig<float>(int, const ContigArgs<float, float>&, int, hipStream_t, int);
+template hipError_t Launch<float>::contig<double>(int, const ContigArgs<float, double>&, int, hipStream_t, int);
 }

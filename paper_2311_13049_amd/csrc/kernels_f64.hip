@@ -3,5 +3,5 @@
 
 namespace vofl {
 template struct Launch<double>;
-template hipError_t Launch<double>::contig<double>(int, const ContigArgs<double, double>&, int, hipStream_t);
+template hipError_t Launch<double>::contig<double>(int, const ContigArgs<double, double>&, int, hipStream_t, int);
 }

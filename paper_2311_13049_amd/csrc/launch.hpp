@@ -24,8 +24,15 @@ constexpr int e_c2r0(int N) { return has5(N) ? 10 : has3(N) ? 12 : (N < 8 ? N : 
 constexpr int e_1d(int N) {
     return has5(N) ? 10 : has3(N) ? (N <= 1536 ? 6 : 12) : (N < 4 ? N : (N <= 2048 ? 4 : 8));
 }
+// The autotuner's alternative for the last-axis pass (contig variant 1): the
+// other of 4 and 8 elements per thread (radix schedules 4-4-4-4 and 8-8-4 at
+// 256) for power-of-two lengths 64..1024; other lengths have none.
+constexpr int e_contig_alt(int N) {
+    return (has3(N) || has5(N) || N < 64 || N > 1024) ? e_contig(N) : (e_contig(N) == 4 ? 8 : 4);
+}
 // pencils per workgroup of k_contig: about 256 threads
-constexpr int p_contig(int N) { return (256 / (N / e_contig(N))) > 0 ? (256 / (N / e_contig(N))) : 1; }
+constexpr int p_contig_e(int N, int E) { return (256 / (N / E)) > 0 ? (256 / (N / E)) : 1; }
+constexpr int p_contig(int N) { return p_contig_e(N, e_contig(N)); }
 
 template <typename T>
 struct Launch {
@@ -37,8 +44,10 @@ struct Launch {
     static int c2r_default(int N);
     // whether an axis-0 variant has its own kernel for length N (else it falls back to 0)
     static bool c2r_variant_exists(int N, int variant);
+    // variant 0: e_contig(N) elements per thread; 1: e_contig_alt(N)
     template <typename TI>
-    static hipError_t contig(int N, const ContigArgs<T, TI>& a, int items, hipStream_t s);
+    static hipError_t contig(int N, const ContigArgs<T, TI>& a, int items, hipStream_t s, int variant = 0);
+    static bool contig_variant_exists(int N, int variant);
     static hipError_t mid(int N, int dir, const MidArgs<T>& a, int planes, int items, hipStream_t s,
                           int variant = 0);
     static int mid_tile(int N, int variant);

@@ -81,22 +81,40 @@ bool contig_args_ok(const ContigArgs<T, TI>& a) {
     return true;
 }
 
+template <typename T, typename TI, int n, int E>
+hipError_t contig_launch(const ContigArgs<T, TI>& a, int items, hipStream_t s) {
+    constexpr int P = p_contig_e(n, E);
+    dim3 grid((a.npencils + P - 1) / P, items);
+    if (contig_streams(a, items)) k_contig<T, TI, n, E, P, true><<<grid, dim3(P * (n / E)), 0, s>>>(a);
+    else k_contig<T, TI, n, E, P><<<grid, dim3(P * (n / E)), 0, s>>>(a);
+    return hipGetLastError();
+}
+
 template <typename T>
 template <typename TI>
-hipError_t Launch<T>::contig(int N, const ContigArgs<T, TI>& a, int items, hipStream_t s) {
+hipError_t Launch<T>::contig(int N, const ContigArgs<T, TI>& a, int items, hipStream_t s, int variant) {
     if (!contig_args_ok(a)) return hipErrorInvalidValue;
     switch (N) {
 #define C_(n)                                                                           \
     case n: {                                                                           \
-        constexpr int E = e_contig(n), P = p_contig(n);                                 \
-        dim3 grid((a.npencils + P - 1) / P, items);                                     \
-        if (contig_streams(a, items)) k_contig<T, TI, n, E, P, true><<<grid, dim3(P * (n / E)), 0, s>>>(a); \
-        else k_contig<T, TI, n, E, P><<<grid, dim3(P * (n / E)), 0, s>>>(a);            \
-        return hipGetLastError();                                                       \
+        if constexpr (e_contig_alt(n) != e_contig(n))                                   \
+            if (variant == 1) return contig_launch<T, TI, n, e_contig_alt(n)>(a, items, s); \
+        return contig_launch<T, TI, n, e_contig(n)>(a, items, s);                       \
     }
         VOFL_MULTI_SIZES(C_)
 #undef C_
         default: return hipErrorInvalidValue;
+    }
+}
+
+template <typename T>
+bool Launch<T>::contig_variant_exists(int N, int variant) {
+    switch (N) {
+#define C_(n)                                                                           \
+    case n: return variant == 0 || (variant == 1 && e_contig_alt(n) != e_contig(n));
+        VOFL_MULTI_SIZES(C_)
+#undef C_
+        default: return false;
     }
 }
 

@@ -240,6 +240,7 @@ struct vofl_plan_s {
     };
     std::vector<GraphEntry> graphs;    // vofl_step_graph cache, oldest first
     int mid_variant = 1;               // k_mid tile variant (1: double-width tiles)
+    int contig_variant = 0;            // last-axis elements per thread (1: the alternative radix schedule)
     // resumable run (vofl_step_begin / advance / end): 0 none; 1 the state is
     // (u_hat, v_hat) at t_n itself (after begin); 2 the state is the one right
     // after the kick of the last step (the step's closing half sub-step pending)
@@ -541,7 +542,7 @@ int apply_multi(vofl_plan_s* p, int op, const TIN* u, T* out, int nf, hipStream_
     a.emit_kind = EMIT_APPLY;
     a.do_prop = 0;
     a.op = op;
-    e = p->timed("contig_apply", s, [&] { return Launch<T>::contig(g.nlast, a, nf, s); });
+    e = p->timed("contig_apply", s, [&] { return Launch<T>::contig(g.nlast, a, nf, s, p->contig_variant); });
     if (e != hipSuccess) return hip_fail(e, "contig launch");
     if ((e = mid<T>(p, "mid_apply_terms", +1, W, AS, p->M + 1, nf, (const cpx<T>*)p->tw[1 % g.ndim], s)) != hipSuccess)
         return hip_fail(e, "mid launch");
@@ -636,7 +637,7 @@ int lffp_seismic_multi(vofl_plan_s* p, double cb0, double ca0, double cf0, doubl
         if (e != hipSuccess) return hip_fail(e, "r2c0 launch");
         if ((e = mid<double>(p, "mid_lffp_fwd", -1, U, g.H, 1, 2 * items, p->tw64[1 % g.ndim], s)) != hipSuccess)
             return hip_fail(e, "mid launch");
-        e = p->timed("contig_lffp", s, [&] { return Launch<T>::contig(g.nlast, a, items, s); });
+        e = p->timed("contig_lffp", s, [&] { return Launch<T>::contig(g.nlast, a, items, s, p->contig_variant); });
         if (e != hipSuccess) return hip_fail(e, "contig launch");
         if ((e = mid<T>(p, "mid_lffp_terms", +1, W, SS, g.nterm, items, (const cpx<T>*)p->tw[1 % g.ndim], s)) !=
             hipSuccess)
@@ -687,7 +688,7 @@ int step_multi(vofl_plan_s* p, T* u, T* v, int nsteps, hipStream_t s) {
         a.emit_kind = emit_terms;
         a.do_prop = 1;
         a.tprop = 0.5 * substep_len_h(p, 0);
-        e = p->timed("contig_init", s, [&] { return Launch<T>::contig(g.nlast, a, items, s); });
+        e = p->timed("contig_init", s, [&] { return Launch<T>::contig(g.nlast, a, items, s, p->contig_variant); });
         if (e != hipSuccess) return hip_fail(e, "contig launch");
     }
 
@@ -719,7 +720,7 @@ int step_multi(vofl_plan_s* p, T* u, T* v, int nsteps, hipStream_t s) {
         a.tprop = last ? 0.5 * ds : 0.5 * (ds + substep_len_h(p, st + 1));
         a.emit_kind = last ? EMIT_EXPORT : emit_terms;
         a.out = W + (last ? (long long)h0 * g.H : 0);
-        e = p->timed("contig_kick", s, [&] { return Launch<T>::contig(g.nlast, a, items, s); });
+        e = p->timed("contig_kick", s, [&] { return Launch<T>::contig(g.nlast, a, items, s, p->contig_variant); });
         if (e != hipSuccess) return hip_fail(e, "contig launch");
     }
     if ((e = mid<T>(p, "mid_export", +1, W + (long long)h0 * g.H, SS, 2, items, twm, s)) != hipSuccess)
@@ -765,7 +766,7 @@ int run_begin_multi(vofl_plan_s* p, const T* u, const T* v, hipStream_t s) {
     a.in_kind = IN_INIT;
     a.emit_kind = EMIT_NONE;
     a.do_prop = 0;
-    e = p->timed("contig_begin", s, [&] { return Launch<T>::contig(g.nlast, a, items, s); });
+    e = p->timed("contig_begin", s, [&] { return Launch<T>::contig(g.nlast, a, items, s, p->contig_variant); });
     return e == hipSuccess ? VOFL_OK : hip_fail(e, "contig launch");
 }
 
@@ -791,7 +792,7 @@ int run_advance_multi(vofl_plan_s* p, int nsteps, int phase, hipStream_t s) {
         a.do_prop = 1;
         const double first = substep_len_h(p, 0);
         a.tprop = phase == 1 ? 0.5 * first : 0.5 * (substep_len_h(p, p->sub - 1) + first);
-        e = p->timed("contig_resume", s, [&] { return Launch<T>::contig(g.nlast, a, items, s); });
+        e = p->timed("contig_resume", s, [&] { return Launch<T>::contig(g.nlast, a, items, s, p->contig_variant); });
         if (e != hipSuccess) return hip_fail(e, "contig launch");
     }
     C2RArgs<T> c = c2r_base<T>(p);
@@ -821,7 +822,7 @@ int run_advance_multi(vofl_plan_s* p, int nsteps, int phase, hipStream_t s) {
         a.do_prop = last ? 0 : 1;
         a.tprop = last ? 0.0 : 0.5 * (ds + substep_len_h(p, st + 1));
         a.emit_kind = last ? EMIT_NONE : emit_terms;
-        e = p->timed(last ? "contig_close" : "contig_kick", s, [&] { return Launch<T>::contig(g.nlast, a, items, s); });
+        e = p->timed(last ? "contig_close" : "contig_kick", s, [&] { return Launch<T>::contig(g.nlast, a, items, s, p->contig_variant); });
         if (e != hipSuccess) return hip_fail(e, "contig launch");
     }
     return VOFL_OK;
@@ -844,7 +845,7 @@ int run_end_multi(vofl_plan_s* p, T* u, T* v, int phase, hipStream_t s) {
     a.emit_kind = EMIT_EXPORT;
     a.do_prop = phase == 2 ? 1 : 0;
     a.tprop = 0.5 * substep_len_h(p, p->sub - 1);
-    e = p->timed("contig_end", s, [&] { return Launch<T>::contig(g.nlast, a, items, s); });
+    e = p->timed("contig_end", s, [&] { return Launch<T>::contig(g.nlast, a, items, s, p->contig_variant); });
     if (e != hipSuccess) return hip_fail(e, "contig launch");
     if ((e = mid<T>(p, "mid_export", +1, W + (long long)h0 * g.H, SS, 2, items, twm, s)) != hipSuccess)
         return hip_fail(e, "mid launch");
@@ -1111,7 +1112,7 @@ int noalloc_fail(int code, const char* msg) { return fail(code, "%s", msg); }
 // ---------------------------------------------------------------------------
 std::string tune_key(const vofl_plan_s* p) {
     std::ostringstream k;
-    k << "vofl1 ndim=" << p->g.ndim << " n=" << p->g.n[0] << "x" << p->g.n[1] << "x" << p->g.n[2]
+    k << "vofl2 ndim=" << p->g.ndim << " n=" << p->g.n[0] << "x" << p->g.n[1] << "x" << p->g.n[2]
       << " M=" << p->M << " prec=" << p->precision << " model=" << p->model << " batch=" << p->g.batch;
     return k.str();
 }
@@ -1126,11 +1127,12 @@ bool tune_cache_lookup(vofl_plan_s* p, const std::string& key) {
         const size_t bar = line.find(" | ");
         if (bar == std::string::npos || line.substr(0, bar) != key) continue;
         std::istringstream rest(line.substr(bar + 3));
-        int c = 0, m = 0;
+        int c = 0, m = 0, cv = 0;
         double ms = 0;
-        if (rest >> c >> m >> ms) {
+        if (rest >> c >> m >> cv >> ms) {
             p->c2r_variant = c;                    // a variant without a kernel runs as 0
             p->mid_variant = (m >= 0 && m <= 2) ? m : 0;
+            p->contig_variant = cv == 1 ? 1 : 0;   // likewise
             p->tuned_ms = ms;
             found = true;  // the last matching line wins
         }
@@ -1170,35 +1172,43 @@ int autotune(vofl_plan_s* p, int steps) {
     const bool timing = p->timing;
     p->timing = false;
     double best = 1e300;
-    int bc = p->c2r_variant, bm = p->mid_variant;
-    for (int c : c2r) {
-        for (int m : mid) {
-            if (rc) break;
-            p->c2r_variant = c;
-            p->mid_variant = m;
-            rc = step_any<T>(p, u, v, 1, s);
-            if (rc) break;
-            (void)hipEventRecord(e0, s);
-            rc = step_any<T>(p, u, v, steps, s);
-            (void)hipEventRecord(e1, s);
-            if (rc) break;
-            e = hipEventSynchronize(e1);
-            if (e != hipSuccess) {
-                rc = hip_fail(e, "autotune run");
-                break;
-            }
-            float ms = 0.f;
-            (void)hipEventElapsedTime(&ms, e0, e1);
-            if (ms < best) {
-                best = ms;
-                bc = c;
-                bm = m;
-            }
+    int bc = p->c2r_variant, bm = p->mid_variant, bv = p->contig_variant;
+    // one candidate: (axis-0 variant, middle-axis tile, last-axis schedule)
+    auto time_one = [&](int c, int m, int cv) {
+        if (rc) return;
+        p->c2r_variant = c;
+        p->mid_variant = m;
+        p->contig_variant = cv;
+        rc = step_any<T>(p, u, v, 1, s);
+        if (rc) return;
+        (void)hipEventRecord(e0, s);
+        rc = step_any<T>(p, u, v, steps, s);
+        (void)hipEventRecord(e1, s);
+        if (rc) return;
+        e = hipEventSynchronize(e1);
+        if (e != hipSuccess) {
+            rc = hip_fail(e, "autotune run");
+            return;
         }
-    }
+        float ms = 0.f;
+        (void)hipEventElapsedTime(&ms, e0, e1);
+        if (ms < best) {
+            best = ms;
+            bc = c;
+            bm = m;
+            bv = cv;
+        }
+    };
+    // axis-0 variants x middle-axis tiles with the default last-axis schedule,
+    // then the last-axis schedules (elements per thread, hence radices) with
+    // the best pair
+    for (int c : c2r)
+        for (int m : mid) time_one(c, m, 0);
+    if (Launch<T>::contig_variant_exists(g.nlast, 1)) time_one(bc, bm, 1);
     p->timing = timing;
     p->c2r_variant = bc;
     p->mid_variant = bm;
+    p->contig_variant = bv;
     p->tuned_ms = (best < 1e300) ? best / steps : 0.0;
     if (s) (void)hipStreamSynchronize(s);
     if (e0) (void)hipEventDestroy(e0);
@@ -1211,7 +1221,7 @@ int autotune(vofl_plan_s* p, int steps) {
     if (rc == VOFL_OK) {
         if (const char* path = std::getenv("VOFL_TUNE_CACHE")) {
             std::ofstream f(path, std::ios::app);
-            f << key << " | " << bc << " " << bm << " " << p->tuned_ms << "\n";
+            f << key << " | " << bc << " " << bm << " " << bv << " " << p->tuned_ms << "\n";
         }
     }
     return rc;
@@ -1323,6 +1333,7 @@ int vofl_plan(const vofl_desc* d, void* stream, vofl_plan_t* out) {
         p->c2r_variant = (d->precision == VOFL_FP32) ? Launch<float>::c2r_default(g.n[0])
                                                      : Launch<double>::c2r_default(g.n[0]);
     if (const char* ev = std::getenv("VOFL_C2R_VARIANT")) p->c2r_variant = std::atoi(ev);
+    if (const char* ev = std::getenv("VOFL_CONTIG_VARIANT")) p->contig_variant = std::atoi(ev) == 1 ? 1 : 0;
     if (const char* ev = std::getenv("VOFL_MID_VARIANT")) {
         // only 0, 1, 2 exist; the launcher's grid and kernel tile must agree
         const int v = std::atoi(ev);
@@ -1635,10 +1646,10 @@ int vofl_kernel_times(vofl_plan_t p, const char** names, double* ms, long long* 
 
 int vofl_plan_info(vofl_plan_t p, double* out, int cap) {
     if (!p || !out) return fail(VOFL_ERR_INVALID, "null argument");
-    const double v[7] = {p->model == VOFL_MODEL_GENERIC ? p->sc_host[0].sig1 : p->sc_host[0].sig1 - 1.0,
+    const double v[8] = {p->model == VOFL_MODEL_GENERIC ? p->sc_host[0].sig1 : p->sc_host[0].sig1 - 1.0,
                          p->sc_host[0].kappa0, p->sc_host[0].beta0, (double)p->g.Nreal, (double)p->g.bytes,
-                         (double)p->c2r_variant, (double)p->mid_variant};
-    for (int i = 0; i < cap && i < 7; ++i) out[i] = v[i];
+                         (double)p->c2r_variant, (double)p->mid_variant, (double)p->contig_variant};
+    for (int i = 0; i < cap && i < 8; ++i) out[i] = v[i];
     return VOFL_OK;
 }
 

@@ -274,10 +274,11 @@ def vofl_kernel_times(plan: int) -> dict:
 
 
 def vofl_plan_info(plan: int) -> dict:
-    out = (ctypes.c_double * 7)()
-    _check(load_library().vofl_plan_info(ctypes.c_void_p(plan), out, 7))
+    out = (ctypes.c_double * 8)()
+    _check(load_library().vofl_plan_info(ctypes.c_void_p(plan), out, 8))
     return dict(mean_order_offset=out[0], kappa0=out[1], beta0=out[2], N=int(out[3]),
-                device_bytes=int(out[4]), c2r_variant=int(out[5]), mid_variant=int(out[6]))
+                device_bytes=int(out[4]), c2r_variant=int(out[5]), mid_variant=int(out[6]),
+                contig_variant=int(out[7]))
 
 
 def vofl_destroy(plan: int) -> None:

@@ -203,8 +203,10 @@ def test_autotuned_plans_pick_listed_variants_and_stay_accurate(c4, tmp_path):
             p = _plan(c4, shots, not big, tune_steps=3)
             info = p.info()
             assert info["c2r_variant"] in (0, 2, 5, 6, 11, 12, 13, 14)
+            assert info["contig_variant"] in (0, 1)
             q = _plan(c4, shots, not big, tune_steps=3)  # served from the cache file
             assert q.info()["c2r_variant"] == info["c2r_variant"]
+            assert q.info()["contig_variant"] == info["contig_variant"]
             u, v = _fields(shots)
             p.step(u, v, 10)
             torch.cuda.synchronize()

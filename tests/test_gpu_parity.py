@@ -346,3 +346,33 @@ def test_mid_variants_apply_and_step(precision, mid_variant):
     say(f"  parity err u {eu:.2e} v {ev:.2e}")
     assert eu <= tol(precision), eu
     assert ev <= tol(precision), ev
+
+
+@pytest.mark.parametrize("contig_variant", [0, 1])
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+@pytest.mark.parametrize("shape", [(8, 16, 256), (16, 512), (8, 1024)])
+def test_last_axis_schedules_apply_and_step(shape, precision, contig_variant):
+    """Both last-axis radix schedules (4 or 8 elements per thread) the
+    autotuner chooses between, against the oracle."""
+    import os
+    lo = tuple(-0.125 * n for n in shape)
+    hi = tuple(0.125 * n for n in shape)
+    Q, gamma = _grf_gamma(shape, lo, hi, 88)
+    u0 = gaussian_pulse(shape, lo, hi, [0.1] * len(shape))
+    say(f"last-axis schedule {contig_variant} {shape} {precision}")
+    os.environ["VOFL_CONTIG_VARIANT"] = str(contig_variant)
+    try:
+        p = _plan(shape, lo, hi, precision, Q=Q, M=5, dt=2e-3, max_batch=2)
+    finally:
+        del os.environ["VOFL_CONTIG_VARIANT"]
+    assert p.info()["contig_variant"] == contig_variant
+    u_in = as_seen(u0, precision)
+    out = host(p.apply(1, dev(u0, precision))).reshape(shape)
+    assert parity_err(out, O.mterm_apply(u_in, 1.0 + gamma, lo, hi, 5)) <= tol(precision)
+    u, v = dev(u0, precision), dev(np.zeros(shape), precision)
+    p.step(u, v, 3)
+    assert p.sync_status() == 0
+    ru, rv = O.tsfp2_seismic(u_in, np.zeros(shape), gamma, 1.0, 1.0, lo, hi, 5, 2e-3, 3)
+    eu, ev = parity_err(host(u), ru), parity_err(host(v), rv)
+    say(f"  parity err u {eu:.2e} v {ev:.2e}")
+    assert eu <= tol(precision) and ev <= tol(precision), (eu, ev)
