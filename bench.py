@@ -113,8 +113,8 @@ def main():
         for _ in range(5):
             b.copy_(a)
         torch.cuda.synchronize()
-        # achieved rate of a plain device copy (the practical HBM ceiling for
-        # a read + write stream on this GPU), HIP events on the current stream
+        # rate of torch's device copy kernel on the same bytes (HIP events on
+        # the current stream), reported beside the counter calibration
         reps = 20
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         e0.record()
@@ -216,6 +216,7 @@ def main():
         "apply_only_b2": head["apply_only"].get("b2"),
         "apply_only": head["apply_only"],
         "step_time_spread": head["spread"],
+        "resumable_chunk": head["resumable_chunk"],
         "roofline": head["roofline"],
         "whole_step": head["whole_step"],
         "kernel_ms_per_step": head["kernel_ms_per_step"],
@@ -281,18 +282,37 @@ def _c3_measure(args, torch, V, dev, c, prec, extras):
 
     spread = None
     apply_rates = {}
+    chunk = None
     if extras:
+        # resumable run: the cost of a 1-step chunk (vofl_step_advance(1),
+        # eager and graph replay) against a steady-state step of vofl_step
+        plan.begin(u, v)
+        plan.advance(2)
+        plan.advance(1, graph=True)  # capture outside the timing
+        torch.cuda.synchronize()
+        res = {}
+        for mode in ("eager", "graph"):
+            reps = 20
+            t0 = time.perf_counter()
+            for _ in range(reps):
+                plan.advance(1, graph=(mode == "graph"))
+            torch.cuda.synchronize()
+            res[f"ms_per_1_step_chunk_{mode}"] = (time.perf_counter() - t0) / reps * 1e3
+        plan.end(u, v)
+        chunk = dict(res, ms_per_steady_step=step_s * 1e3,
+                     ratio_eager=res["ms_per_1_step_chunk_eager"] / (step_s * 1e3),
+                     ratio_graph=res["ms_per_1_step_chunk_graph"] / (step_s * 1e3))
         # spread of the per-step time: 20 chunks of 10 steps, each bracketed
         # by HIP events on the stream the plan launches on
-        chunk, nchunks = 10, 20
+        cs, nchunks = 10, 20
         evs = [torch.cuda.Event(enable_timing=True) for _ in range(nchunks + 1)]
         evs[0].record()
         for i in range(nchunks):
-            plan.step(u, v, chunk)
+            plan.step(u, v, cs)
             evs[i + 1].record()
         torch.cuda.synchronize()
-        per_step = sorted(evs[i].elapsed_time(evs[i + 1]) / chunk for i in range(nchunks))
-        spread = {"chunk_steps": chunk, "chunks": nchunks, "median_ms_per_step": float(np.median(per_step)),
+        per_step = sorted(evs[i].elapsed_time(evs[i + 1]) / cs for i in range(nchunks))
+        spread = {"chunk_steps": cs, "chunks": nchunks, "median_ms_per_step": float(np.median(per_step)),
                   "p99_ms_per_step": float(np.percentile(per_step, 99)), "min_ms_per_step": per_step[0],
                   "max_ms_per_step": per_step[-1]}
     # apply-only throughput for b = 1, 2 (the L1/L2 pair size) and 4 fields
@@ -328,6 +348,7 @@ def _c3_measure(args, torch, V, dev, c, prec, extras):
                         for k, (ms, nl) in ktimes.items() if algorithmic_bytes(k, n, M, elt) > 0},
         "apply_only": apply_rates,
         "spread": spread,
+        "resumable_chunk": chunk,
     }
 
 
@@ -438,6 +459,23 @@ def bench_c4(args, torch, V, dev):
         fn(steps)
         torch.cuda.synchronize()
         timings[name] = time.perf_counter() - t0
+    # the whole batched step sequence (both groups, forked onto the plans'
+    # streams and joined) captured as one graph and replayed
+    one_graph_error = None
+    try:
+        cap = torch.cuda.Stream()
+        cg = torch.cuda.CUDAGraph()
+        torch.cuda.synchronize()
+        with torch.cuda.graph(cg, stream=cap):
+            eager(steps)
+        cg.replay()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        cg.replay()
+        torch.cuda.synchronize()
+        timings["one_graph_batch"] = time.perf_counter() - t0
+    except Exception as exc:  # capture refused by the runtime: report it
+        one_graph_error = str(exc)[:300]
     # each group alone on the current stream: eager steps against graph
     # replays of the same steps (the graph's own cost per launch)
     per_group = {}
@@ -502,6 +540,7 @@ def bench_c4(args, torch, V, dev):
                                "with their own GRF Q, M=12, FP32, dt=5e-4"},
         "ms_per_step_by_mode": {k: t / steps * 1e3 for k, t in timings.items()},
         "per_group_alone": per_group,
+        "one_graph_error": one_graph_error,
         "applies_per_s": 2 * nshots / step_s,
         "gpts_M_per_s": Ntot * c["M"] * 2 / step_s / 1e9,
         "roofline": {"bound": "hbm", "achieved": bstep / step_s / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s",

@@ -90,15 +90,21 @@ __device__ __forceinline__ void nt_store(cpx<T>* p, cpx<T> c) {
 // pointwise helpers (FP64)
 // ---------------------------------------------------------------------------
 
+// The rarely taken overdamped branch of damped_flow, kept out of line; it
+// returns its pair by value (in registers: reference outputs of an
+// out-of-line call go through per-lane stack memory on every point, and the
+// wait on that load also waits for every vector memory access in flight).
+struct CoshSinh {
+    double C, S;
+};
+__device__ __noinline__ CoshSinh overdamped_cs(double w2m, double t) {
+    const double w = sqrt(w2m);
+    return {cosh(w * t), sinh(w * t) / w};
+}
+
 // Exact flow over time t of u' = v, v' = -kappa0 P1 u - beta0 P2 v (one mode).
 // b = beta0 P2/2, q = kappa0 P1, w^2 = q - b^2; the k = 0 mode (P1 = P2 = 0)
 // gives u += t v (eq. (3.11)); beta0 = 0 gives the rotation (3.10).
-__device__ __noinline__ void overdamped_cs(double w2m, double t, double& C, double& S) {
-    const double w = sqrt(w2m);
-    C = cosh(w * t);
-    S = sinh(w * t) / w;
-}
-
 __device__ __forceinline__ void damped_flow(double P1, double P2, double kappa0, double beta0,
                                             double t, double& g11, double& g12, double& g21,
                                             double& g22) {
@@ -113,7 +119,9 @@ __device__ __forceinline__ void damped_flow(double P1, double P2, double kappa0,
         C = cs;
         S = sn / w;
     } else if (w2 < 0.0) {
-        overdamped_cs(-w2, t, C, S);
+        const CoshSinh r = overdamped_cs(-w2, t);
+        C = r.C;
+        S = r.S;
     } else {
         C = 1.0;
         S = t;
@@ -227,9 +235,13 @@ __global__ __launch_bounds__(P*(N / E)) void k_contig(ContigArgs<T, TI> a) {
     constexpr bool WV = (TP <= 64) && (64 % TP == 0);
     // the inverse transforms of the terms read this thread's twiddles from a
     // per-position LDS table (conflict-free, consecutive lanes read
-    // consecutive entries) instead of the strided length-N table
+    // consecutive entries) instead of the strided length-N table, for the
+    // radix-4/8 schedules with at most 16 twiddles per thread. The schedules
+    // of 10 and 12 elements per thread (lengths with a factor 5 or 3) read
+    // the length-N table: with the per-position table the 768-point pass
+    // measured 3.7 times slower.
     constexpr int TWC = tw_count(N, E);
-    constexpr bool TWT = TWC > 0;
+    constexpr bool TWT = E <= 8 && TWC > 0 && TWC <= 16;
     __shared__ cpx<T> twt_s[TWT ? TWC * TP : 1];
     if constexpr (TWT) {
         if (lp == 0) thread_twiddles_at<T, N, E, 1>(twt_s, t, tw_s);
