@@ -24,6 +24,7 @@ from __future__ import annotations
 
 import argparse
 import hashlib
+import itertools
 import json
 import os
 import sys
@@ -39,15 +40,20 @@ WORKLOAD = ("3D periodic [-16,16)^3, 256^3, M=16, two-layer Q (20 above / 100 be
             "x (1 +- 5% seeded noise), Gaussian pulse u0, v0 = 0, c0 = omega0 = 1, dt = 1e-3")
 
 
+# device-code sources of the solver's kernels and their launch shapes (host
+# code, the allocation-free 1D entry point and the streaming probe do not
+# change what a step kernel reads or writes)
+KERNEL_SOURCES = ("fft_engine.hpp", "kernels.hpp", "launch.hpp", "launch_impl.hpp",
+                  "kernels_f32.hip", "kernels_f64.hip")
+
+
 def kernel_source_hash() -> str:
-    """Hash of the device-code sources (kernels and their launch shapes); host
-    code does not change what a kernel reads or writes."""
+    """Hash of the step kernels' device-code sources."""
     h = hashlib.sha256()
     csrc = os.path.join(ROOT, "paper_2311_13049_amd", "csrc")
-    for name in sorted(os.listdir(csrc)):
-        if name.endswith((".hpp", ".hip")):
-            with open(os.path.join(csrc, name), "rb") as f:
-                h.update(f.read())
+    for name in KERNEL_SOURCES:
+        with open(os.path.join(csrc, name), "rb") as f:
+            h.update(f.read())
     return h.hexdigest()[:16]
 
 
@@ -90,6 +96,8 @@ def main():
     ap.add_argument("--requests", type=int, default=200, help="c5: requests in the trace")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain device copy of 1 GiB five times (HBM counter calibration)")
+    ap.add_argument("--stream-probe", action="store_true",
+                    help="only measure the read, write and copy stream rates of the library's probe kernels")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py runs on one GPU only: the workload is one grid per device, and this "
@@ -127,6 +135,8 @@ def main():
                           "launches": 5 + reps, "copy_ms": ms, "copy_GBps_read_plus_write": 2 * nbytes / ms / 1e6}),
               flush=True)
         return
+    if args.stream_probe:
+        return stream_probe(torch, V, dev)
     if args.workload == "c4":
         return bench_c4(args, torch, V, dev)
     if args.workload == "c5":
@@ -220,6 +230,7 @@ def main():
         "roofline": head["roofline"],
         "whole_step": head["whole_step"],
         "kernel_ms_per_step": head["kernel_ms_per_step"],
+        "kernel_GBps": head["kernel_GBps"],
         "status": head["status"],
         f"{other}_path": side,
         "accuracy": accuracy,
@@ -404,6 +415,38 @@ def _c5_short(args, torch, V, dev, count=30, step_scale=0.1):
             "served": {k: served.get(k) for k in keys},
             "plain_fp64_single_solve": {k: plain.get(k) for k in keys},
             "workload": f"first {count} requests of the c5 Poisson stream (200 req/s), steps x {step_scale}"}
+
+
+def stream_probe(torch, V, dev, nbytes=4 << 30, reps=10):
+    """Read, write and copy streams of 4 GiB through the library's probe
+    kernels, over several grid sizes, 4 or 16 accesses in flight per lane,
+    with and without non-temporal accesses;
+    HIP events on the current stream. Rates count the bytes each stream
+    moves (copy: read + write)."""
+    src = torch.empty(nbytes // 4, dtype=torch.float32, device=dev).fill_(1.0)
+    dst = torch.empty_like(src)
+    cur = torch.cuda.current_stream().cuda_stream
+    rows = []
+    for kind, name, moved in ((V.VOFL_PROBE_READ, "read", nbytes), (V.VOFL_PROBE_WRITE, "write", nbytes),
+                              (V.VOFL_PROBE_COPY, "copy", 2 * nbytes)):
+        for blocks, nt, deep in itertools.product((512, 1024, 2048, 4096, 8192), (False, True), (False, True)):
+            flags = (V.VOFL_PROBE_NONTEMPORAL if nt else 0) | (V.VOFL_PROBE_DEEP if deep else 0)
+            def run():
+                V.vofl_stream_probe(kind, src.data_ptr(), dst.data_ptr(), nbytes, blocks, flags, cur)
+            run()
+            run()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            for _ in range(reps):
+                run()
+            e1.record()
+            torch.cuda.synchronize()
+            ms = e0.elapsed_time(e1) / reps
+            rows.append({"stream": name, "blocks": blocks, "nontemporal": nt, "deep": deep, "ms": ms,
+                         "GBps": moved / ms / 1e6})
+    assert torch.equal(dst, src), "copy stream result differs from its source"
+    best = {n: max((r for r in rows if r["stream"] == n), key=lambda r: r["GBps"]) for n in ("read", "write", "copy")}
+    print(json.dumps({"stream_probe_bytes": nbytes, "reps": reps, "best": best, "all": rows}), flush=True)
 
 
 def _fork_join(torch, streams, fns):

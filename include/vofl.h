@@ -260,6 +260,27 @@ int vofl_step_batch(vofl_plan_t* plans, void** u, void** v, const int* nsteps,
 int vofl_apply_noalloc(int n, double lo, double hi, const double* s, int M, int precision,
                        const void* u, void* out, int nfields, void* stream);
 
+/* Measurement support (computes nothing of the method): stream `bytes`
+ * through HBM as a plain read (kind VOFL_PROBE_READ: src is read, dst holds
+ * one float per workgroup that is written only for one improbable sum),
+ * a plain write (VOFL_PROBE_WRITE: dst is filled with vector i holding
+ * (i mod 1024) + 0, 1, 2, 3; src unused) or a one-to-one copy
+ * (VOFL_PROBE_COPY: src to dst), with 16 bytes per lane per access,
+ * `blocks` workgroups of 256 threads striding over the buffer, 4 accesses in
+ * flight per lane (16 with VOFL_PROBE_DEEP in flags) and non-temporal loads
+ * and stores with VOFL_PROBE_NONTEMPORAL. Device pointers, 16-byte aligned;
+ * bytes a positive multiple of 16; blocks in 1..2^20; src and dst must not
+ * overlap. Used to measure the read, write and copy rates that each pass's
+ * own read/write mix is set against. Asynchronous on stream;
+ * VOFL_ERR_INVALID for arguments outside these ranges. */
+#define VOFL_PROBE_READ  0
+#define VOFL_PROBE_WRITE 1
+#define VOFL_PROBE_COPY  2
+#define VOFL_PROBE_NONTEMPORAL 1
+#define VOFL_PROBE_DEEP        2
+int vofl_stream_probe(int kind, const void* src, void* dst, size_t bytes, int blocks, int flags,
+                      void* stream);
+
 /* Synchronize stream, then report VOFL_ERR_UNSTABLE if the plan's
  * non-finite flag is set (the flag is cleared by the read). */
 int vofl_sync_status(vofl_plan_t plan, void* stream);

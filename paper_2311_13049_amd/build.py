@@ -20,7 +20,7 @@ LIB = os.path.join(HERE, "libvofl.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 
-SOURCES = ["kernels_f32.hip", "kernels_f64.hip", "vofl_plan.cpp", "noalloc.hip"]
+SOURCES = ["kernels_f32.hip", "kernels_f64.hip", "vofl_plan.cpp", "noalloc.hip", "stream_probe.hip"]
 
 FLAGS = [
     f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC", "-pthread",

@@ -233,22 +233,28 @@ __global__ __launch_bounds__(P*(N / E)) void k_contig(ContigArgs<T, TI> a) {
     // a pencil's TP threads are consecutive and TP divides 64: every
     // transform stays inside one wavefront
     constexpr bool WV = (TP <= 64) && (64 % TP == 0);
-    // the inverse transforms of the terms read this thread's twiddles from a
+    // Twiddles of the terms' inverse transforms (radix-4/8 schedules with at
+    // most 16 per thread): for a pencil of one wavefront or less, from a
     // per-position LDS table (conflict-free, consecutive lanes read
-    // consecutive entries) instead of the strided length-N table, for the
-    // radix-4/8 schedules with at most 16 twiddles per thread. The schedules
-    // of 10 and 12 elements per thread (lengths with a factor 5 or 3) read
-    // the length-N table: with the per-position table the 768-point pass
-    // measured 3.7 times slower.
+    // consecutive entries); for longer pencils, from registers loaded once
+    // (the table would take TP x 16 entries of LDS: 48 KiB for a 1024-point
+    // FP64 pencil, a third of the workgroups per CU). The schedules of 10
+    // and 12 elements per thread (factors 5 or 3) read the length-N table:
+    // with the per-position table the 768-point pass was 3.7 times slower.
     constexpr int TWC = tw_count(N, E);
-    constexpr bool TWT = E <= 8 && TWC > 0 && TWC <= 16;
+    constexpr bool TWFEW = E <= 8 && TWC > 0 && TWC <= 16;
+    constexpr bool TWT = TWFEW && TP <= 64;
+    constexpr bool TWREG = TWFEW && !TWT;
     __shared__ cpx<T> twt_s[TWT ? TWC * TP : 1];
     if constexpr (TWT) {
         if (lp == 0) thread_twiddles_at<T, N, E, 1>(twt_s, t, tw_s);
         __syncthreads();
     }
+    cpx<T> twr[TWREG ? TWC : 1];
+    if constexpr (TWREG) load_twiddles<T, N, E, TWC>(twr, t, tw_s);
     auto inv_fft = [&](cpx<T> (&x)[E]) __attribute__((always_inline)) {
         if constexpr (TWT) fft_pencil_t<T, N, E, +1, LPT, WV>(x, t, lds, twt_s);
+        else if constexpr (TWREG) fft_pencil_r<T, N, E, +1, LPT, WV, TWC>(x, t, lds, twr);
         else fft_pencil<T, N, E, +1, LPT, WV>(x, t, lds, tw_s);
     };
 

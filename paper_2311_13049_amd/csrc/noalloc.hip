@@ -15,7 +15,7 @@
 #include "vofl.h"
 
 namespace vofl {
-int noalloc_fail(int code, const char* msg);  // vofl_plan.cpp: sets vofl_last_error
+int api_fail(int code, const char* msg);  // vofl_plan.cpp: sets vofl_last_error
 }
 
 namespace {
@@ -91,7 +91,7 @@ unsigned char* device_scratch(int& rc) {
     int dev = 0;
     hipError_t e = hipGetDevice(&dev);
     if (e != hipSuccess || dev < 0 || dev >= NOALLOC_MAX_DEVICES) {
-        rc = vofl::noalloc_fail(VOFL_ERR_DEVICE, "no current HIP device");
+        rc = vofl::api_fail(VOFL_ERR_DEVICE, "no current HIP device");
         return nullptr;
     }
     std::lock_guard<std::mutex> lock(g_mtx);
@@ -99,7 +99,7 @@ unsigned char* device_scratch(int& rc) {
         void* ptr = nullptr;
         e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
         if (e != hipSuccess || !ptr) {
-            rc = vofl::noalloc_fail(VOFL_ERR_DEVICE, "hipGetSymbolAddress(scratch) failed");
+            rc = vofl::api_fail(VOFL_ERR_DEVICE, "hipGetSymbolAddress(scratch) failed");
             return nullptr;
         }
         g_scratch[dev] = static_cast<unsigned char*>(ptr);
@@ -112,13 +112,13 @@ int apply_noalloc(int n, double lo, double hi, const double* s, int M, const voi
                   hipStream_t st) {
     const Layout l = layout(n, sizeof(cpx<T>));
     if (l.total > NOALLOC_SCRATCH_BYTES)
-        return vofl::noalloc_fail(VOFL_ERR_INVALID, "grid too large for the allocation-free apply's scratch");
+        return vofl::api_fail(VOFL_ERR_INVALID, "grid too large for the allocation-free apply's scratch");
     int rc = VOFL_OK;
     unsigned char* base = device_scratch(rc);
     if (!base) return rc;
     k_noalloc_prep<T><<<dim3(1), dim3(256), 0, st>>>(s, n, hi - lo, base, l);
     hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return vofl::noalloc_fail(VOFL_ERR_DEVICE, "prep launch failed");
+    if (e != hipSuccess) return vofl::api_fail(VOFL_ERR_DEVICE, "prep launch failed");
     vofl::Args1D<T> a{};
     a.u_in = static_cast<const T*>(u);
     a.u_out = static_cast<T*>(out);
@@ -135,7 +135,7 @@ int apply_noalloc(int n, double lo, double hi, const double* s, int M, const voi
     a.invN = 1.0 / double(n);
     a.sub = 1;
     e = vofl::Launch<T>::d1_apply(n, a, nfields, st);
-    if (e != hipSuccess) return vofl::noalloc_fail(VOFL_ERR_DEVICE, "apply launch failed");
+    if (e != hipSuccess) return vofl::api_fail(VOFL_ERR_DEVICE, "apply launch failed");
     return VOFL_OK;
 }
 
@@ -143,17 +143,17 @@ int apply_noalloc(int n, double lo, double hi, const double* s, int M, const voi
 
 extern "C" int vofl_apply_noalloc(int n, double lo, double hi, const double* s, int M, int precision,
                                   const void* u, void* out, int nfields, void* stream) {
-    if (!s || !u || !out) return vofl::noalloc_fail(VOFL_ERR_INVALID, "s, u and out must be device pointers");
-    if (u == out) return vofl::noalloc_fail(VOFL_ERR_INVALID, "out must not alias u");
-    if (n < 2 || n % 2) return vofl::noalloc_fail(VOFL_ERR_INVALID, "n must be even and >= 2");
-    if (!(hi > lo)) return vofl::noalloc_fail(VOFL_ERR_INVALID, "the box must satisfy lo < hi");
-    if (M < 0 || M > 64) return vofl::noalloc_fail(VOFL_ERR_INVALID, "M must be in [0, 64]");
-    if (nfields < 1 || nfields > 65535) return vofl::noalloc_fail(VOFL_ERR_INVALID, "nfields must be in [1, 65535]");
+    if (!s || !u || !out) return vofl::api_fail(VOFL_ERR_INVALID, "s, u and out must be device pointers");
+    if (u == out) return vofl::api_fail(VOFL_ERR_INVALID, "out must not alias u");
+    if (n < 2 || n % 2) return vofl::api_fail(VOFL_ERR_INVALID, "n must be even and >= 2");
+    if (!(hi > lo)) return vofl::api_fail(VOFL_ERR_INVALID, "the box must satisfy lo < hi");
+    if (M < 0 || M > 64) return vofl::api_fail(VOFL_ERR_INVALID, "M must be in [0, 64]");
+    if (nfields < 1 || nfields > 65535) return vofl::api_fail(VOFL_ERR_INVALID, "nfields must be in [1, 65535]");
     if (precision != VOFL_FP64 && precision != VOFL_FP32)
-        return vofl::noalloc_fail(VOFL_ERR_INVALID, "precision must be VOFL_FP64 or VOFL_FP32");
+        return vofl::api_fail(VOFL_ERR_INVALID, "precision must be VOFL_FP64 or VOFL_FP32");
     const bool fp32 = precision == VOFL_FP32;
     if (!(fp32 ? vofl::Launch<float>::supported_1d(n) : vofl::Launch<double>::supported_1d(n)))
-        return vofl::noalloc_fail(VOFL_ERR_UNSUPPORTED, "no compiled 1D transform of this length");
+        return vofl::api_fail(VOFL_ERR_UNSUPPORTED, "no compiled 1D transform of this length");
     hipStream_t st = static_cast<hipStream_t>(stream);
     return fp32 ? apply_noalloc<float>(n, lo, hi, s, M, u, out, nfields, st)
                 : apply_noalloc<double>(n, lo, hi, s, M, u, out, nfields, st);

@@ -1103,8 +1103,9 @@ int run_end_any(vofl_plan_s* p, void* u, void* v, int phase, hipStream_t s) {
 }  // namespace
 
 namespace vofl {
-// error reporting for the allocation-free entry point (noalloc.hip)
-int noalloc_fail(int code, const char* msg) { return fail(code, "%s", msg); }
+// error reporting for the entry points defined outside this file (noalloc.hip,
+// stream_probe.hip)
+int api_fail(int code, const char* msg) { return fail(code, "%s", msg); }
 }  // namespace vofl
 
 // ---------------------------------------------------------------------------

@@ -26,6 +26,11 @@ VOFL_FP64 = 0
 VOFL_FP32 = 1
 VOFL_MODEL_SEISMIC = 0
 VOFL_MODEL_GENERIC = 1
+VOFL_PROBE_READ = 0
+VOFL_PROBE_WRITE = 1
+VOFL_PROBE_COPY = 2
+VOFL_PROBE_NONTEMPORAL = 1
+VOFL_PROBE_DEEP = 2
 VOFL_OP_S1 = 1
 VOFL_OP_S2 = 2
 
@@ -35,6 +40,7 @@ ABI_FUNCTIONS = (
     "vofl_step_begin", "vofl_step_advance", "vofl_step_end", "vofl_lffp_start", "vofl_lffp_step",
     "vofl_cnfp_step", "vofl_step_batch", "vofl_sync_status", "vofl_set_timing", "vofl_kernel_times",
     "vofl_plan_info", "vofl_destroy", "vofl_last_error", "vofl_version", "vofl_apply_noalloc",
+    "vofl_stream_probe",
 )
 
 _c_double_p = ctypes.POINTER(ctypes.c_double)
@@ -109,13 +115,14 @@ def load_library():
     lib.vofl_destroy.argtypes = [vp]
     lib.vofl_apply_noalloc.argtypes = [ctypes.c_int, ctypes.c_double, ctypes.c_double, vp, ctypes.c_int,
                                        ctypes.c_int, vp, vp, ctypes.c_int, vp]
+    lib.vofl_stream_probe.argtypes = [ctypes.c_int, vp, vp, ctypes.c_size_t, ctypes.c_int, ctypes.c_int, vp]
     lib.vofl_last_error.restype = ctypes.c_char_p
     lib.vofl_version.restype = ctypes.c_char_p
     for name in ("vofl_plan", "vofl_plan_footprint", "vofl_apply", "vofl_step", "vofl_step_graph", "vofl_solve",
                  "vofl_step_begin", "vofl_step_advance", "vofl_step_end", "vofl_lffp_start", "vofl_lffp_step",
                  "vofl_cnfp_step",
                  "vofl_step_batch", "vofl_sync_status", "vofl_set_timing", "vofl_kernel_times",
-                 "vofl_plan_info", "vofl_destroy", "vofl_apply_noalloc"):
+                 "vofl_plan_info", "vofl_destroy", "vofl_apply_noalloc", "vofl_stream_probe"):
         getattr(lib, name).restype = ctypes.c_int
     _lib = lib
     return lib
@@ -202,6 +209,12 @@ def vofl_apply_noalloc(n: int, lo: float, hi: float, s_ptr: int, M: int, precisi
     _check(load_library().vofl_apply_noalloc(int(n), float(lo), float(hi), ctypes.c_void_p(s_ptr), int(M),
                                              int(precision), ctypes.c_void_p(u_ptr), ctypes.c_void_p(out_ptr),
                                              int(nfields), ctypes.c_void_p(stream)))
+
+
+def vofl_stream_probe(kind: int, src_ptr: int, dst_ptr: int, nbytes: int, blocks: int, flags: int = 0,
+                      stream=0) -> None:
+    _check(load_library().vofl_stream_probe(int(kind), ctypes.c_void_p(src_ptr), ctypes.c_void_p(dst_ptr),
+                                            int(nbytes), int(blocks), int(flags), ctypes.c_void_p(stream)))
 
 
 def vofl_step_begin(plan: int, u_ptr: int, v_ptr: int, stream=0) -> None:

@@ -109,6 +109,27 @@ def test_null_plan_arguments_are_rejected():
     assert "NULL" in V.vofl_last_error()
 
 
+def test_stream_probe_rejects_bad_arguments_on_the_host():
+    """Argument checks come before any device call (none of these reaches a GPU)."""
+    lib = V.load_library()
+    ok16 = 4096  # a 16-byte aligned stand-in address; never dereferenced here
+    cases = [
+        (7, ok16, ok16, 1024, 64),                  # unknown kind
+        (V.VOFL_PROBE_COPY, ok16, ok16, 0, 64),     # no bytes
+        (V.VOFL_PROBE_COPY, ok16, ok16, 1000, 64),  # not a multiple of 16
+        (V.VOFL_PROBE_COPY, ok16, ok16, 1024, 0),   # no workgroups
+        (V.VOFL_PROBE_COPY, None, ok16, 1024, 64),  # copy without a source
+        (V.VOFL_PROBE_WRITE, None, None, 1024, 64),  # nothing to write to
+        (V.VOFL_PROBE_READ, ok16 + 8, ok16, 1024, 64),  # misaligned source
+    ]
+    for kind, src, dst, nbytes, blocks in cases:
+        assert lib.vofl_stream_probe(kind, src, dst, nbytes, blocks, 0, None) == V.VOFL_ERR_INVALID
+        assert "vofl_stream_probe" in V.vofl_last_error()
+    # an unknown flag bit
+    assert lib.vofl_stream_probe(V.VOFL_PROBE_COPY, ok16, ok16, 1024, 64, 4, None) == V.VOFL_ERR_INVALID
+    assert "vofl_stream_probe" in V.vofl_last_error()
+
+
 def test_plan_without_device_reports_device_error():
     """On a host without a GPU the plan fails cleanly with VOFL_ERR_DEVICE."""
     d, keep = _desc()

@@ -80,3 +80,31 @@ def test_kernel_times_count_the_launches_of_one_step_call():
     p.step(u, v, 2)
     torch.cuda.synchronize()
     assert p.kernel_times()["c2r0_kick"][1] == 5
+
+
+def test_stream_probe_streams_move_the_bytes_they_name():
+    """The measurement probe: a copy reproduces its source, a write fills the
+    documented pattern, a read leaves the destination alone; every kind with
+    a ragged tail (bytes not a multiple of one trip), both depths and both
+    cache policies."""
+    import torch
+    require_gpu()
+    from paper_2311_13049_amd import vofl as V
+    cur = torch.cuda.current_stream().cuda_stream
+    nvec = 3 * 256 * 16 * 7 + 13          # 16-byte vectors: several trips and a tail
+    src = torch.randn(nvec * 4, device="cuda")
+    for flags in (0, V.VOFL_PROBE_NONTEMPORAL, V.VOFL_PROBE_DEEP, V.VOFL_PROBE_NONTEMPORAL | V.VOFL_PROBE_DEEP):
+        for blocks in (1, 5, 64):
+            say(f"stream probe nvec={nvec} blocks={blocks} flags={flags}")
+            dst = torch.full_like(src, -3.0)
+            V.vofl_stream_probe(V.VOFL_PROBE_READ, src.data_ptr(), dst.data_ptr(), nvec * 16, blocks, flags, cur)
+            torch.cuda.synchronize()
+            assert bool((dst == -3.0).all())
+            V.vofl_stream_probe(V.VOFL_PROBE_COPY, src.data_ptr(), dst.data_ptr(), nvec * 16, blocks, flags, cur)
+            torch.cuda.synchronize()
+            assert torch.equal(dst, src)
+            V.vofl_stream_probe(V.VOFL_PROBE_WRITE, 0, dst.data_ptr(), nvec * 16, blocks, flags, cur)
+            torch.cuda.synchronize()
+            i = torch.arange(nvec, device="cuda") & 1023
+            want = (i.float()[:, None] + torch.arange(4, device="cuda").float()[None, :]).reshape(-1)
+            assert torch.equal(dst, want)

@@ -169,6 +169,43 @@ def test_graph_replays_equal_eager_steps(c4):
         p.close()
 
 
+def test_step_batch_captured_as_one_graph_equals_eager(c4):
+    """vofl_step_batch of both groups (forked onto the plans' streams and
+    joined) captured into one graph by the caller, replayed 3 times with other
+    device work and host synchronisation in between: every replay equals the
+    same steps run eagerly."""
+    import torch
+    small, big = _group(c4, False)[:8], _group(c4, True)[:3]
+    pa, pb = _plan(c4, small, True), _plan(c4, big, False)
+    ua, va = _fields(small)
+    ub, vb = _fields(big)
+    ea, fa, eb, fb = ua.clone(), va.clone(), ub.clone(), vb.clone()
+    _step_batch([pa, pb], [ea, eb], [fa, fb], [1, 1])  # first call: internal streams exist
+    _step_batch([pa, pb], [ua, ub], [va, vb], [1, 1])
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    cap = torch.cuda.Stream()
+    say("capture vofl_step_batch (8 x 512^2 and 3 x 768^2, 4 and 3 steps)")
+    with torch.cuda.graph(g, stream=cap):
+        _step_batch([pa, pb], [ua, ub], [va, vb], [4, 3])
+    torch.cuda.synchronize()
+    # the capture ran nothing: the fields still hold the 1-step state
+    assert torch.equal(ua, ea) and torch.equal(ub, eb)
+    scratch = torch.randn(1 << 20, device="cuda")
+    for rep in range(3):
+        say(f"one-graph replay {rep}")
+        g.replay()
+        scratch.mul_(1.0001).add_(0.5)
+        _step_batch([pa, pb], [ea, eb], [fa, fb], [4, 3])
+        torch.cuda.synchronize()
+        for x, y in ((ua, ea), (va, fa), (ub, eb), (vb, fb)):
+            assert torch.equal(x, y)
+    assert pa.sync_status() == 0 and pb.sync_status() == 0
+    del g
+    pa.close()
+    pb.close()
+
+
 def test_graph_cache_keys_on_buffers_and_steps(c4):
     """Different (u, v, nsteps) get their own graphs; more than the cache holds
     still gives correct results (oldest graphs are dropped)."""
