@@ -57,8 +57,8 @@ def kernel_source_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def algorithmic_bytes(cls: str, n: int, M: int, elt: int) -> float:
-    """Bytes one launch of a kernel class must move at least (read + write once).
+def algorithmic_rw(cls: str, n: int, M: int, elt: int) -> tuple:
+    """(read, write) bytes one launch of a kernel class must move at least.
 
     N real points, H = (n/2+1) n^2 complex half-spectrum elements, complex of
     2*elt bytes; state FP64 complex (16 B); delta FP64, A and B elt bytes.
@@ -69,14 +69,61 @@ def algorithmic_bytes(cls: str, n: int, M: int, elt: int) -> float:
     nterm = 2 * (M + 1)
     table = {
         # kick axis-0 pass: read 2(M+1) term slots + delta, A, B; write dv half
-        "c2r0_kick": nterm * H * c + N * (8 + 2 * elt) + H * c,
+        "c2r0_kick": (nterm * H * c + N * (8 + 2 * elt), H * c),
         # middle-axis pass over the 2(M+1) term slots (in place)
-        "mid_terms": 2 * nterm * H * c,
-        "mid_dv": 2 * H * c,
+        "mid_terms": (nterm * H * c, nterm * H * c),
+        "mid_dv": (H * c, H * c),
         # last-axis pass: read dv half + state (u_hat, v_hat), write state + 2(M+1) slots
-        "contig_kick": H * c + 4 * H * 16 + nterm * H * c,
+        "contig_kick": (H * c + 2 * H * 16, 2 * H * 16 + nterm * H * c),
     }
-    return float(table.get(cls, 0.0))
+    r, w = table.get(cls, (0, 0))
+    return float(r), float(w)
+
+
+def algorithmic_bytes(cls: str, n: int, M: int, elt: int) -> float:
+    """Bytes one launch of a kernel class must move at least (read + write once)."""
+    return sum(algorithmic_rw(cls, n, M, elt))
+
+
+# probe settings that reached the highest rates on this GPU (a sweep over
+# grid sizes, depth and cache policy: bench.py --stream-probe)
+STREAM_CONFIGS = {"read": [(512, 1), (1024, 1)], "write": [(8192, 0), (4096, 2)], "copy": [(512, 0), (8192, 1)]}
+
+
+def measure_streams(torch, V, dev, nbytes=4 << 30, reps=10):
+    """Best measured read, write and copy stream rates (GB/s) of the library's
+    probe kernels over 4 GiB, HIP events on the current stream."""
+    src = torch.empty(nbytes // 4, dtype=torch.float32, device=dev).fill_(1.0)
+    dst = torch.empty_like(src)
+    cur = torch.cuda.current_stream().cuda_stream
+    kinds = {"read": V.VOFL_PROBE_READ, "write": V.VOFL_PROBE_WRITE, "copy": V.VOFL_PROBE_COPY}
+    out = {}
+    for name, cfgs in STREAM_CONFIGS.items():
+        best = 0.0
+        for blocks, flags in cfgs:
+            for _ in range(2):
+                V.vofl_stream_probe(kinds[name], src.data_ptr(), dst.data_ptr(), nbytes, blocks, flags, cur)
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            for _ in range(reps):
+                V.vofl_stream_probe(kinds[name], src.data_ptr(), dst.data_ptr(), nbytes, blocks, flags, cur)
+            e1.record()
+            torch.cuda.synchronize()
+            moved = 2 * nbytes if name == "copy" else nbytes
+            best = max(best, moved / (e0.elapsed_time(e1) / reps) / 1e6)
+        out[f"{name}_GBps"] = best
+    del src, dst
+    torch.cuda.empty_cache()
+    out["note"] = ("best rates of plain read, write and copy streams over 4 GiB (vofl_stream_probe); a pass "
+                   "moving R read and W written bytes is set against (R + W) / (R / read + W / write)")
+    return out
+
+
+def mix_bound(rw, streams):
+    """Rate (GB/s) of a stream of R read and W written bytes when reads and
+    writes run at the measured stream rates one after the other."""
+    r, w = rw
+    return (r + w) / (r / streams["read_GBps"] + w / streams["write_GBps"])
 
 
 def main():
@@ -155,6 +202,18 @@ def main():
     head = _c3_measure(args, torch, V, dev, c, args.precision, extras=not args.no_extras)
     side = None if args.no_extras else _c3_measure(args, torch, V, dev, c, other, extras=True)
     N = n ** 3
+    streams = None
+    if not args.no_extras:
+        # each kernel against a stream of its own read/write mix at the
+        # measured read and write rates of this GPU
+        streams = measure_streams(torch, V, dev)
+        for res in (head, side):
+            elt = 4 if res["precision"] == "fp32" else 8
+            res["kernel_of_stream_mix_bound"] = {
+                k: gbps / mix_bound(algorithmic_rw(k, n, M, elt), streams) for k, gbps in res["kernel_GBps"].items()}
+            rf = res["roofline"]
+            rf["stream_mix_bound_GBps"] = mix_bound(algorithmic_rw(rf["kernel"], n, M, elt), streams)
+            rf["of_stream_mix_bound"] = rf["achieved"] / rf["stream_mix_bound_GBps"]
 
     cpu = None
     cpu_mt = None
@@ -231,6 +290,8 @@ def main():
         "whole_step": head["whole_step"],
         "kernel_ms_per_step": head["kernel_ms_per_step"],
         "kernel_GBps": head["kernel_GBps"],
+        "kernel_of_stream_mix_bound": head.get("kernel_of_stream_mix_bound"),
+        "streams": streams,
         "status": head["status"],
         f"{other}_path": side,
         "accuracy": accuracy,
