@@ -117,7 +117,10 @@ typedef struct vofl_plan_s* vofl_plan_t;
  * 5, 6, 11, 12, 13, 14) and VOFL_MID_VARIANT (middle-axis tile: 0, 1, 2)
  * force a kernel variant instead of the default (a variant without a kernel
  * for the plan's length runs as variant 0) and VOFL_CONTIG_VARIANT (last-axis
- * radix schedule: 0, 1); results agree to rounding. */
+ * radix schedule: 0, 1); results agree to rounding. The plan keeps its half
+ * spectra (2D/3D) with rows along axis 0 padded by 128 bytes when a row spans
+ * 4 KiB or more; VOFL_HALF_ROW_PAD (complex elements, 0 = none) sets the
+ * padding instead (results are the same; the layout is internal). */
 int vofl_plan(const vofl_desc* desc, void* stream, vofl_plan_t* out);
 
 /* Device bytes a plan for desc would allocate (same validation as vofl_plan,

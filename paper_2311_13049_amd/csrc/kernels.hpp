@@ -184,7 +184,8 @@ struct ContigArgs {
     cpx<double>* V;          // spectral state v_hat
     cpx<T>* out;             // output slots: item b, slot s at out + b*out_istride + s*H
     long long out_istride;
-    long long H;             // complex elements of one half field
+    long long H;             // complex elements one half field occupies
+    long long rs;            // row stride of a half field along axis 0 (>= n1 * N)
     int npencils;            // pencils of one field
     int n1;                  // pencils per k0 plane (3D: n1, 2D: 1)
     const double* mu2_0;     // mu^2 of axis 0 by bin
@@ -228,7 +229,8 @@ __global__ __launch_bounds__(P*(N / E)) void k_contig(ContigArgs<T, TI> a) {
     const int k0 = pc / a.n1;
     const int k1 = pc % a.n1;
     const double m2base = a.mu2_0[k0] + (a.mu2_1 ? a.mu2_1[k1] : 0.0);
-    const long long pen = (long long)pc * N;
+    // pencil (k0, k1) of a half field: row k0 (stride rs), k1-th run of N
+    const long long pen = (long long)k0 * a.rs + (long long)k1 * N;
     const SolveScalars sc = a.sc[bi * a.sc_stride];
     // a pencil's TP threads are consecutive and TP divides 64: every
     // transform stays inside one wavefront
@@ -432,6 +434,7 @@ struct MidArgs {
     long long istride;
     int nf;                 // fields per item
     long long H;
+    long long rs;           // stride of the k0 planes (>= n1 * n2)
     int n2;                 // columns of a k0 plane (last axis length)
     int tiles_per_plane;    // ceil(n2 / W)
     const cpx<T>* tw;       // axis-1 twiddles
@@ -453,8 +456,7 @@ __global__ __launch_bounds__(W*(N / E)) void k_mid(MidArgs<T> a) {
     const int colc = active ? col : 0;
     const int item = blockIdx.y / a.nf;
     const int f = blockIdx.y % a.nf;
-    cpx<T>* base = a.buf + (long long)item * a.istride + (long long)f * a.H +
-                   (long long)plane * N * a.n2 + colc;
+    cpx<T>* base = a.buf + (long long)item * a.istride + (long long)f * a.H + (long long)plane * a.rs + colc;
     const LdsColumn<T, W> lds{lds_raw + c};
     cpx<T> v[E];
 #pragma unroll
@@ -483,8 +485,9 @@ struct R2CArgs {
     const TR* in2;          // optional second fields: the input is c1 in + c2 in2 (FP64)
     double c1, c2;
     long long Nreal;
-    cpx<double>* out;       // FP64 half spectra: item b at out + b*H
+    cpx<double>* out;       // FP64 half spectra: item b at out + b*H, row k at + k*rs
     long long H;
+    long long rs;
     int inner;              // columns (product of the other axes)
     const cpx<double>* tw;  // axis-0 twiddles (FP64)
 };
@@ -523,7 +526,7 @@ __global__ __launch_bounds__(W*(N / E)) void k_r2c0(R2CArgs<TR> a) {
             if (k <= N / 2) {
                 cpx<double> z = v[e];
                 if (k == 0 || k == N / 2) z.y = 0.0;
-                dst[(long long)k * a.inner] = z;
+                dst[(long long)k * a.rs] = z;
             }
         }
     }
@@ -534,9 +537,10 @@ __global__ __launch_bounds__(W*(N / E)) void k_r2c0(R2CArgs<TR> a) {
 // ---------------------------------------------------------------------------
 template <typename T>
 struct C2RArgs {
-    const cpx<T>* in;       // half slots: item b, slot s at in + b*istride + s*H
+    const cpx<T>* in;       // half slots: item b, slot s at in + b*istride + s*H, row k at + k*rs
     long long istride;
     long long H;
+    long long rs;           // row stride of the half slots (>= inner); physical rows: inner
     int inner;
     const cpx<T>* tw;       // axis-0 twiddles
     int mode, M, model;
@@ -686,11 +690,11 @@ void k_c2r0(C2RArgs<T> a) {
             // rows t + TP e for e < E/2, and the Nyquist row (used by t = 0
             // only; the other positions load the same cached row and drop it)
             const int r = (e == E / 2) ? N / 2 : t + TP * e;
-            return (unsigned(r) * unsigned(a.inner) + unsigned(colc)) * unsigned(sizeof(cpx<T>));
+            return (unsigned(r) * unsigned(a.rs) + unsigned(colc)) * unsigned(sizeof(cpx<T>));
         }
         const int k = t + TP * e;
         const int r = (k <= N / 2) ? k : N - k;
-        return (unsigned(r) * unsigned(a.inner) + unsigned(colc)) * unsigned(sizeof(cpx<T>));
+        return (unsigned(r) * unsigned(a.rs) + unsigned(colc)) * unsigned(sizeof(cpx<T>));
     };
 #pragma unroll
     for (int e = 0; e < NL; ++e) roff[e] = row_off(e);
@@ -1002,7 +1006,7 @@ void k_c2r0(C2RArgs<T> a) {
             if (k <= N / 2) {
                 cpx<T> w = z[e];
                 if (k == 0 || k == N / 2) w.y = T(0);
-                dst[(long long)k * a.inner] = w;
+                dst[(long long)k * a.rs] = w;
             }
         }
     }
@@ -1064,7 +1068,7 @@ __global__ __launch_bounds__(64 * NW_) void k_c2r0w(C2RArgs<T> a) {
         const int i = threadIdx.x + j * NT;
         const int row = (i < HR * W) ? i / W : 0;
         const int cg = col0 + i % W;
-        soff[j] = (unsigned(row) * unsigned(a.inner) + unsigned(cg < a.inner ? cg : 0)) *
+        soff[j] = (unsigned(row) * unsigned(a.rs) + unsigned(cg < a.inner ? cg : 0)) *
                   unsigned(sizeof(cpx<T>));
     }
     cpx<T> pf1[ST], pf2[ST];
@@ -1228,7 +1232,7 @@ __global__ __launch_bounds__(64 * NW_) void k_c2r0w(C2RArgs<T> a) {
     cpx<T>* dst = a.dv_out + (long long)item * a.istride;
     for (int i = threadIdx.x; i < HR * W; i += NT) {
         const int row = i / W, cg = col0 + i % W;
-        if (cg < a.inner) dst[(long long)row * a.inner + cg] = stg[i];
+        if (cg < a.inner) dst[(long long)row * a.rs + cg] = stg[i];
     }
 }
 

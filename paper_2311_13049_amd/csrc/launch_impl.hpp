@@ -84,6 +84,7 @@ bool contig_args_ok(const ContigArgs<T, TI>& a) {
 template <typename T, typename TI, int n, int E>
 hipError_t contig_launch(const ContigArgs<T, TI>& a, int items, hipStream_t s) {
     constexpr int P = p_contig_e(n, E);
+    if (a.rs < (long long)a.n1 * n) return hipErrorInvalidValue;  // rows hold n1 pencils
     dim3 grid((a.npencils + P - 1) / P, items);
     if (contig_streams(a, items)) k_contig<T, TI, n, E, P, true><<<grid, dim3(P * (n / E)), 0, s>>>(a);
     else k_contig<T, TI, n, E, P><<<grid, dim3(P * (n / E)), 0, s>>>(a);
@@ -138,6 +139,7 @@ void mid_launch(int dir, bool nt, dim3 grid, const MidArgs<T>& a, hipStream_t s)
 template <typename T>
 hipError_t Launch<T>::mid(int N, int dir, const MidArgs<T>& a, int planes, int items,
                           hipStream_t s, int variant) {
+    if (a.rs < (long long)N * a.n2) return hipErrorInvalidValue;  // a plane holds N rows of n2
     switch (N) {
 #define C_(n)                                                                           \
     case n: {                                                                           \
@@ -179,6 +181,7 @@ int Launch<T>::mid_tile(int N, int variant) {
 
 template <typename T>
 hipError_t Launch<T>::r2c0(int N, const R2CArgs<T>& a, int items, hipStream_t s) {
+    if (a.rs < a.inner) return hipErrorInvalidValue;
     switch (N) {
 #define C_(n)                                                                           \
     case n: {                                                                           \
@@ -251,6 +254,7 @@ hipError_t c2r0w_mode(const C2RArgs<T>& a, int items, hipStream_t s) {
 // fall back to 0 in the export mode.
 template <typename T>
 hipError_t Launch<T>::c2r0(int N, const C2RArgs<T>& a, int items, hipStream_t s, int variant) {
+    if (a.rs < a.inner) return hipErrorInvalidValue;
     switch (N) {
 #define C_(n)                                                                           \
     case n: {                                                                           \
