@@ -279,7 +279,7 @@ def main():
         "vs_baseline": None,
         "dtype": "f32" if prec == "fp32" else "f64",
         "data": "synthetic",
-        "config": {"workload": WORKLOAD if n == 256 else WORKLOAD.replace("256^3", f"{n}^3"),
+        "config": {"workload": WORKLOAD.replace("256^3", f"{n}^3").replace("M=16", f"M={M}"),
                    "grid": [n, n, n], "M": M, "precision": prec, "solver": "TSFP2 (3.13)"},
         "gpts_M_per_s": head["gpts_M_per_s"],
         "apply_only_b2": head["apply_only"].get("b2"),
