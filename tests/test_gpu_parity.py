@@ -376,3 +376,42 @@ def test_last_axis_schedules_apply_and_step(shape, precision, contig_variant):
     eu, ev = parity_err(host(u), ru), parity_err(host(v), rv)
     say(f"  parity err u {eu:.2e} v {ev:.2e}")
     assert eu <= tol(precision) and ev <= tol(precision), (eu, ev)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+@pytest.mark.parametrize("shape", [(16, 32, 64), (32, 512), (64, 1000)])
+def test_half_row_padding_does_not_change_results(shape, precision):
+    """The padded stride of the half spectra's axis-0 rows is a layout choice
+    only: plans with the default padding, with none and with a larger one
+    give bit-identical applies, TSFP2 steps and leap-frog steps."""
+    import os
+    lo = tuple(-0.125 * n for n in shape)
+    hi = tuple(0.125 * n for n in shape)
+    Q, gamma = _grf_gamma(shape, lo, hi, 91)
+    u0 = gaussian_pulse(shape, lo, hi, [0.1] * len(shape))
+    X = mesh(shape, lo, hi)
+    s = 1.0 + 0.2 * np.sin(np.pi * X[0] / 4)
+    results, sizes = [], []
+    for pad in (None, "0", "24"):
+        say(f"half-row padding {pad} {shape} {precision}")
+        if pad is not None:
+            os.environ["VOFL_HALF_ROW_PAD"] = pad
+        try:
+            p = _plan(shape, lo, hi, precision, Q=Q, M=5, dt=2e-3, max_batch=2)
+            pg = _plan(shape, lo, hi, precision, model="generic", s=s, kappa=1.0, lam=0.5, M=5, dt=2e-3)
+        finally:
+            os.environ.pop("VOFL_HALF_ROW_PAD", None)
+        sizes.append(p.info()["device_bytes"])
+        out = host(p.apply(1, dev(u0, precision)))
+        u, v = dev(u0, precision), dev(np.zeros(shape), precision)
+        p.step(u, v, 3)
+        up, uc = pg.lffp_start(dev(u0, precision), dev(np.zeros(shape), precision))
+        pg.lffp_step(up, uc, 3)
+        assert p.sync_status() == 0 and pg.sync_status() == 0
+        results.append((out, host(u), host(v), host(uc), host(up)))
+        p.close()
+        pg.close()
+    assert sizes[1] < sizes[2]  # no pad < a 24-element pad
+    for r in results[1:]:
+        for a, b in zip(results[0], r):
+            assert np.array_equal(a, b)
