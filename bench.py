@@ -130,7 +130,7 @@ def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=50)
-    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--n", type=int, default=256)
     ap.add_argument("--M", type=int, default=16)
     ap.add_argument("--precision", default=None,
@@ -609,7 +609,7 @@ def bench_c4(args, torch, V, dev):
         n0 = g["shots"][0]["shape"][0]
         Ns, Hs, cb, nterm = n0 * n0, (n0 // 2 + 1) * n0, 8, 2 * (c["M"] + 1)
         bstep += len(g["shots"]) * (nterm * Hs * cb + Ns * 16 + Hs * cb + Hs * cb + 64 * Hs + nterm * Hs * cb)
-    # the survey's unfused model: (2M+3) real-field transforms, one read and
+    # the unfused model: (2M+3) real-field transforms, one read and
     # one write of the field per axis pass (an effective rate, not HBM bytes)
     bstep_model = (2 * c["M"] + 3) * 2 * 2 * Ntot * 4
 

@@ -227,7 +227,7 @@ struct vofl_plan_s {
     double* LS = nullptr;              // leap-frog FP64 state: u^{n-1} of every solve, then u^n
     void* cnv = nullptr;               // Crank-Nicolson vectors (CN_VECTORS x N, one solve at a time)
     int coef_item = 0;                 // solve whose coefficients single-field launches use
-                                       // (set by the Crank-Nicolson driver; else 0)
+                                       // (set by the Crank-Nicolson solver; else 0)
     double* cns = nullptr;             // Crank-Nicolson reduction scalars
     int sub = 1;                       // sub-steps per step (3: fourth-order composition)
     double w1 = 1.0, w0 = 1.0;         // composition weights
