@@ -309,11 +309,14 @@ bool Launch<T>::c2r_variant_exists(int N, int variant) {
     }
 }
 
-// Default axis-0 variant: each stored row loaded once. The paired layout on
-// the narrowest tile whose rows still fill a 128-byte line (13: half-width
-// tiles, the FP64 case; 11: full width), else the LDS-staged loads (14),
-// else direct loads (0). Narrower tiles give more workgroups per CU at the
-// same register count; rows shorter than a line would be fetched twice.
+// Default axis-0 variant: each stored row loaded once. Columns of 768 points
+// and more stage their rows through LDS (14: measured faster there, e.g. the
+// 1024^2 FP64 kick 0.116 -> 0.105 ms, where the tiles are 4 columns wide);
+// shorter ones use the paired layout on the narrowest tile whose rows still
+// fill a 128-byte line (13: half-width tiles, the FP64 case; 11: full
+// width), else the LDS-staged loads (14), else direct loads (0). Narrower
+// tiles give more workgroups per CU at the same register count; rows shorter
+// than a line would be fetched twice.
 template <typename T>
 int Launch<T>::c2r_default(int N) {
     switch (N) {
@@ -321,6 +324,7 @@ int Launch<T>::c2r_default(int N) {
     case n: {                                                                           \
         constexpr int W = c2r_width<T, n>(), E = e_c2r0(n);                             \
         constexpr int W2 = (W >= 8) ? W / 2 : W;                                        \
+        if (n >= 768 && E % 2 == 0) return 14;                                          \
         if (W2 != W && paired_ok<n, E, W2>() && W2 * int(sizeof(cpx<T>)) >= 128) return 13; \
         if (paired_ok<n, E, W>()) return 11;                                            \
         return (E % 2 == 0) ? 14 : 0;                                                   \
