@@ -9,14 +9,15 @@
 namespace vofl {
 
 // Elements per thread of each kernel class for a transform length N (the
-// last-axis kernel uses 4 at 256: one 64-thread pencil per wavefront, fewer
-// registers per thread than 8, so more wavefronts per SIMD). Lengths
+// last-axis kernel uses 8 at 256, with LDS layouts free of bank conflicts;
+// the 4-per-thread schedule, one 64-thread pencil per wavefront, is the
+// autotuner's alternative and measured no faster at 256^3). Lengths
 // with a factor 3 (3 * 2^k) use 12 elements per thread (radix 4 stages and
 // one radix-3 stage); lengths with a factor 5 (1000 = 2^3 5^3) use 10
 // (radix-5 and radix-2 stages, 100 threads per pencil).
 constexpr bool has3(int N) { return N % 3 == 0; }
 constexpr bool has5(int N) { return N % 5 == 0; }
-constexpr int e_contig(int N) { return has5(N) ? 10 : has3(N) ? 12 : (N < 8 ? N : ((N >= 1024 || N == 256) ? 4 : 8)); }
+constexpr int e_contig(int N) { return has5(N) ? 10 : has3(N) ? 12 : (N < 8 ? N : (N >= 1024 ? 4 : 8)); }
 constexpr int e_mid(int N) { return has5(N) ? 10 : has3(N) ? 12 : (N < 16 ? N : 16); }
 constexpr int e_r2c0(int N) { return has5(N) ? 10 : has3(N) ? 12 : (N < 16 ? N : 16); }
 constexpr int e_c2r0(int N) { return has5(N) ? 10 : has3(N) ? 12 : (N < 8 ? N : 8); }
