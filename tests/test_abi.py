@@ -98,6 +98,33 @@ def test_valid_descriptors_and_footprint_formula():
     assert b == expect
 
 
+def test_footprint_counts_padded_half_rows(monkeypatch):
+    """Half-spectrum rows along axis 0 that span 4 KiB or more are padded by
+    128 bytes (VOFL_HALF_ROW_PAD overrides the pad, in complex elements)."""
+    n0, n1, M = 16, 512, 4
+    g = np.full(n0 * n1, 0.1)
+
+    def footprint(precision, rs, n1=n1):
+        celt = 8 if precision == "fp32" else 16
+        elt = celt // 2
+        H = (n0 // 2 + 1) * rs
+        slots = max(2 * (M + 1) + 3, 1 * (M + 1))
+        return ((n0 + n1) * (celt + 16 + 8) + n0 * n1 * (8 + 2 * elt) + 64 + 256 + slots * H * celt
+                + 2 * H * 16 + 2 * n0 * n1 * 8)
+
+    for precision, celt in (("fp32", 8), ("fp64", 16)):
+        d, keep = _desc(shape=(n0, n1), gamma=g, precision=precision)
+        assert V.vofl_plan_footprint(d) == footprint(precision, n1 + 128 // celt)
+        monkeypatch.setenv("VOFL_HALF_ROW_PAD", "0")
+        assert V.vofl_plan_footprint(d) == footprint(precision, n1)
+        monkeypatch.setenv("VOFL_HALF_ROW_PAD", "24")
+        assert V.vofl_plan_footprint(d) == footprint(precision, n1 + 24)
+        monkeypatch.delenv("VOFL_HALF_ROW_PAD")
+    # rows under 4 KiB are not padded (32 FP64 columns: 512 bytes)
+    d, keep = _desc(shape=(16, 32), gamma=np.full(512, 0.1), precision="fp64")
+    assert V.vofl_plan_footprint(d) == footprint("fp64", 32, n1=32)
+
+
 def test_null_plan_arguments_are_rejected():
     lib = V.load_library()
     assert lib.vofl_apply(None, 1, None, None, 1, None) == V.VOFL_ERR_INVALID
