@@ -730,34 +730,34 @@ void k_c2r0(C2RArgs<T> a) {
                 m1[e] = shfl(q1[e]);
                 m2[e] = shfl(q2[e]);
             }
-            const bool t0 = t == 0, th = t == TP / 2;
+            // Y = a + i b from the rows a (slot 1) and b (slot 2) of element
+            // e: rows k <= N/2 as loaded (lo), rows k > N/2 as the conjugate
+            // of the mirror row N - k
+            auto pair_lo = [&](cpx<T> a, cpx<T> b) __attribute__((always_inline)) -> cpx<T> {
+                return two ? cpx<T>{a.x - b.y, a.y + b.x} : a;
+            };
+            auto pair_hi = [&](cpx<T> a, cpx<T> b) __attribute__((always_inline)) -> cpx<T> {
+                return two ? cpx<T>{a.x + b.y, b.x - a.y} : cpx<T>{a.x, -a.y};
+            };
+            // positions other than 0 and TP/2: rows t + TP e for e < E/2 are
+            // this thread's loads; the mirror rows of the others are the
+            // partner's loads of elements E - 1 - e
 #pragma unroll
-            for (int e = 0; e < E; ++e) {
-                cpx<T> pa, pb;
-                bool lo, edge = false;
-                if (e < E / 2) {
-                    pa = q1[e];
-                    pb = q2[e];
-                    lo = true;
-                    edge = t0 && e == 0;
-                } else if (e == E / 2) {
-                    const cpx<T> o1 = th ? q1[E / 2 - 1] : m1[E / 2 - 1];
-                    const cpx<T> o2 = th ? q2[E / 2 - 1] : m2[E / 2 - 1];
-                    pa = t0 ? q1[E / 2] : o1;
-                    pb = t0 ? q2[E / 2] : o2;
-                    lo = t0;
-                    edge = t0;
-                } else {
-                    const cpx<T> o1 = th ? q1[E - 1 - e] : m1[E - 1 - e];
-                    const cpx<T> o2 = th ? q2[E - 1 - e] : m2[E - 1 - e];
-                    pa = t0 ? q1[E - e] : o1;
-                    pb = t0 ? q2[E - e] : o2;
-                    lo = false;
-                }
-                const T ax = pa.x, ay = edge ? T(0) : pa.y;
-                const T bx = two ? pb.x : T(0);
-                const T by = (two && !edge) ? pb.y : T(0);
-                y[e] = {lo ? ax - by : ax + by, lo ? ay + bx : bx - ay};
+            for (int e = 0; e < E; ++e)
+                y[e] = (e < E / 2) ? pair_lo(q1[e], q2[e]) : pair_hi(m1[E - 1 - e], m2[E - 1 - e]);
+            // positions 0 and TP/2 (two lanes of one wavefront per column
+            // group): position 0 holds rows 0 and N/2 (real: zero imaginary
+            // parts) and mirrors itself at TP (E - e); TP/2 mirrors itself
+            if (t == 0) {
+                const cpx<T> a0 = {q1[0].x, T(0)}, b0 = {q2[0].x, T(0)};
+                const cpx<T> an = {q1[E / 2].x, T(0)}, bn = {q2[E / 2].x, T(0)};
+                y[0] = pair_lo(a0, b0);
+                y[E / 2] = pair_lo(an, bn);
+#pragma unroll
+                for (int e = E / 2 + 1; e < E; ++e) y[e] = pair_hi(q1[E - e], q2[E - e]);
+            } else if (t == TP / 2) {
+#pragma unroll
+                for (int e = E / 2; e < E; ++e) y[e] = pair_hi(q1[E - 1 - e], q2[E - 1 - e]);
             }
             return;
         }
