@@ -108,3 +108,30 @@ def test_stream_probe_streams_move_the_bytes_they_name():
             i = torch.arange(nvec, device="cuda") & 1023
             want = (i.float()[:, None] + torch.arange(4, device="cuda").float()[None, :]).reshape(-1)
             assert torch.equal(dst, want)
+
+
+def test_arguments_outside_their_domain_are_refused_and_leave_outputs_alone():
+    """Calls with a field count outside [1, max_batch], a negative step count
+    or an unknown operator return VOFL_ERR_INVALID before any launch, and the
+    caller's buffers keep their values; zero steps is a no-op."""
+    import torch
+    from paper_2311_13049_amd import vofl as V
+    p, _ = _plan(max_batch=2)
+    lib = V.load_library()
+    u = dev(gaussian_pulse(SHAPE, LO, HI, (0.0, 0.0)), "fp64")
+    v = torch.zeros_like(u)
+    out = torch.full((3,) + SHAPE, 7.0, dtype=torch.float64, device="cuda")
+    u3 = torch.stack([u, u, u]).contiguous()
+    s = torch.cuda.current_stream().cuda_stream
+    h = p.handle
+    say("domain checks of vofl_apply / vofl_step")
+    assert lib.vofl_apply(h, V.VOFL_OP_S1, u3.data_ptr(), out.data_ptr(), 0, s) == V.VOFL_ERR_INVALID
+    assert lib.vofl_apply(h, V.VOFL_OP_S1, u3.data_ptr(), out.data_ptr(), 3, s) == V.VOFL_ERR_INVALID
+    assert lib.vofl_apply(h, 3, u3.data_ptr(), out.data_ptr(), 1, s) == V.VOFL_ERR_INVALID
+    assert lib.vofl_step(h, u.data_ptr(), v.data_ptr(), -1, s) == V.VOFL_ERR_INVALID
+    u_before = u.clone()
+    assert lib.vofl_step(h, u.data_ptr(), v.data_ptr(), 0, s) == V.VOFL_OK
+    torch.cuda.synchronize()
+    assert bool((out == 7.0).all())
+    assert torch.equal(u, u_before) and bool((v == 0).all())
+    assert p.sync_status() == 0
