@@ -239,10 +239,11 @@ __global__ __launch_bounds__(P*(N / E)) void k_contig(ContigArgs<T, TI> a) {
     // most 16 per thread): for a pencil of one wavefront or less, from a
     // per-position LDS table (conflict-free, consecutive lanes read
     // consecutive entries); for longer pencils, from registers loaded once
-    // (the table would take TP x 16 entries of LDS: 48 KiB for a 1024-point
-    // FP64 pencil, a third of the workgroups per CU). The schedules of 10
-    // and 12 elements per thread (factors 5 or 3) read the length-N table:
-    // with the per-position table the 768-point pass was 3.7 times slower.
+    // (the table holds TP entries per twiddle: 12 x 256 x 16 bytes = 48 KiB
+    // for a 1024-point FP64 pencil, a third of the workgroups per CU). The
+    // schedules of 10 and 12 elements per thread (factors 5 or 3) read the
+    // length-N table: with the per-position table the 768-point pass was 3.7
+    // times slower.
     constexpr int TWC = tw_count(N, E);
     constexpr bool TWFEW = E <= 8 && TWC > 0 && TWC <= 16;
     constexpr bool TWT = TWFEW && TP <= 64;
